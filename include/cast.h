@@ -1,0 +1,196 @@
+/*
+ * cast.h -- C ABI of the MI355X (gfx950) fused-gate state-vector engine.
+ *
+ * The engine applies sequences of k-qubit gates (k = 1..6, 2^k x 2^k complex
+ * matrices) to a 2^n-amplitude state held in device memory, after an optional
+ * host-side agglomerative gate-fusion pass (Sec. III, Alg. 1).  It also
+ * evaluates Pauli-sum expectation values and adjoint-method gradients of
+ * parametrised circuits, one circuit or a batch of them per call.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - State layout (Sec. II-A, Eq. 1): amplitude x (0 <= x < 2^n) is stored at
+ *    element x, qubit q is bit q of x (little-endian).  Amplitudes are
+ *    interleaved complex numbers: (re, im) as two doubles for CAST_C128 or two
+ *    floats for CAST_C64 -- the memory layout of torch.complex128 / complex64.
+ *  - Gate matrices are always passed as host FP64: 2^k x 2^k, row-major,
+ *    interleaved (re, im), so 2 * 4^k doubles.  Bit i of a row/column index
+ *    belongs to qubits[i]; qubit lists need not be sorted.  A k-qubit gate
+ *    acts on the 2^{n-k} groups of amplitudes that agree off its qubits
+ *    (Eq. 3).  Matrices are not checked for unitarity.
+ *  - Errors: every function returns cast_status (0 = CAST_OK, < 0 = error)
+ *    and never aborts or throws.  cast_last_error() returns a thread-local
+ *    message for the last failing call on the calling thread.  Arguments are
+ *    validated before any device work is queued; a failing call leaves its
+ *    outputs untouched unless stated otherwise.
+ *  - Streams: every state carries a HIP stream (NULL = the default stream).
+ *    Device work is queued on it in call order.  Calls marked "synchronous"
+ *    wait for the stream before returning; the others only queue work.
+ *  - Host arrays passed in are copied (or fully consumed) before the call
+ *    returns; the caller may free them immediately.
+ */
+#ifndef CAST_H
+#define CAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int cast_status;
+enum {
+    CAST_OK = 0,
+    CAST_EINVAL = -1,       /* bad argument: range, NULL, duplicate qubit, size mismatch */
+    CAST_ENOMEM = -2,       /* device (or the CAST_MAX_DEVICE_BYTES cap) cannot hold it */
+    CAST_EHIP = -3,         /* a HIP runtime call failed; message has hipGetErrorString */
+    CAST_EUNSUPPORTED = -4, /* valid request with no kernel for it */
+    CAST_ESTATE = -5        /* object in the wrong state (e.g. destroyed state) */
+};
+
+typedef enum { CAST_C64 = 1, CAST_C128 = 2 } cast_dtype;
+
+typedef struct cast_sv cast_sv;       /* opaque state vector (owning or borrowing) */
+typedef struct cast_fused cast_fused; /* opaque fused-gate list, ready to apply */
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *cast_last_error(void);
+
+/* ------------------------------------------------------------------ states */
+
+/* Allocates a 2^n state of dtype `dt` (1 <= n <= 34) on the current HIP
+ * device and sets it to |0...0>.  `hip_stream` (hipStream_t or NULL) is used
+ * for all work on this state.  The caller owns *out and frees it with
+ * sv_destroy.  CAST_ENOMEM if the allocation fails or exceeds the byte cap in
+ * the environment variable CAST_MAX_DEVICE_BYTES. */
+cast_status sv_create(int n, cast_dtype dt, void *hip_stream, cast_sv **out);
+
+/* Wraps existing device memory (2^n amplitudes of dtype `dt`, 16-byte
+ * aligned) without copying or taking ownership: the caller keeps the memory
+ * alive until sv_destroy.  Contents are left as they are. */
+cast_status sv_wrap(void *dev_ptr, int n, cast_dtype dt, void *hip_stream, cast_sv **out);
+
+/* Frees an owning state (or forgets a wrapped one).  NULL-safe. */
+void sv_destroy(cast_sv *sv);
+
+/* Copies `bytes` (= 2^n * amplitude size) of interleaved amplitudes from host
+ * memory into the state.  Synchronous. */
+cast_status sv_copy_from_host(cast_sv *sv, const void *host, size_t bytes);
+
+/* Copies the whole state to host memory (`bytes` = 2^n * amplitude size).
+ * Synchronous. */
+cast_status sv_copy_to_host(const cast_sv *sv, void *host, size_t bytes);
+
+/* Sets the state to the basis state |index>.  Queued on the state's stream. */
+cast_status sv_set_basis(cast_sv *sv, uint64_t index);
+
+/* Device pointer, qubit count and dtype of a state (any output may be NULL). */
+cast_status sv_info(const cast_sv *sv, void **dev_ptr, int *n, cast_dtype *dt);
+
+/* ------------------------------------------------------------------ gates */
+
+/* Applies one k-qubit gate (1 <= k <= 6; Eq. 3) in place: each group of 2^k
+ * amplitudes that agree off `qubits` is multiplied by `matrix`.  The matrix is
+ * analysed on the host (zero/one snapping, XOR-subspace block structure) and
+ * copied to the device in the state's dtype; zero blocks are skipped and
+ * identity blocks are neither read nor written.  Queued on the state's stream
+ * (the staging buffer is kept alive by the library until the work is done). */
+cast_status apply_gate(cast_sv *sv, const int *qubits, int k, const double *matrix);
+
+/* Fills `out` (2 * 4^k doubles) with the matrix of a standard gate, in the
+ * index convention above.  Names: id h x y z s t p u3 rx ry rz rxx ryy rzz cx
+ * cz cp swap.  `params` holds the gate's angles (u3: theta, phi, lambda;
+ * rotations, p, cp: one angle; R(a) = exp(-i a G / 2)).  *k receives the
+ * arity.  CAST_EINVAL for an unknown name. */
+cast_status gate_matrix(const char *name, const double *params, int *k, double *out);
+
+/* A gate in a circuit.  Fixed gates carry `matrix` (host FP64, layout above)
+ * and param_id = -1.  Parametrised rotations carry matrix = NULL, param_id
+ * >= 0 and `generator`: the Pauli letter of qubit i in bits 2i..2i+1
+ * (1 = X, 2 = Y, 3 = Z); the gate is exp(-i * param_coeff * theta[param_id] *
+ * G / 2). */
+typedef struct {
+    int k;
+    int qubits[6];
+    const double *matrix;
+    int param_id;
+    double param_coeff;
+    int generator;
+} cast_gate;
+
+/* Options of the host fusion pass (Sec. III; Table 2 "Gate fusion"). */
+typedef struct {
+    int k_max;            /* largest fused gate, 1..6 (1 = no fusion) */
+    double opcount_cap;   /* reject fusions whose op count exceeds it (<= 0: none) */
+    double zero_tol;      /* |x| <= zero_tol snaps a real scalar to 0 */
+    double one_tol;       /* |x -+ 1| <= one_tol snaps a real scalar to +-1 */
+    int agglomerative;    /* grow the size limit 2 .. k_max (else k_max at once) */
+    int multi_traversal;  /* repeat each traversal until nothing fuses */
+    int cost_model;       /* 0: size-only; 1: adaptive (tuned cost table) */
+} cast_fusion_opts;
+
+/* Default options: k_max 5, no cap, tolerances 1e-14, agglomerative and
+ * multi-traversal on, size-only. */
+void fusion_opts_default(cast_fusion_opts *opts);
+
+/* Fuses a circuit of fixed gates (param_id must be -1; parametrised gates are
+ * bound first by the caller) on n qubits into a list of gates of at most
+ * k_max qubits whose product equals the circuit's unitary (Alg. 1 with the
+ * agglomerative schedule of Sec. III-B).  Matrix products are FP64.  The
+ * result is analysed for the device but holds no device memory until it is
+ * first applied.  The caller owns *out (fused_destroy). */
+cast_status fuse_circuit(int n, const cast_gate *gates, size_t n_gates,
+                         const cast_fusion_opts *opts, cast_fused **out);
+
+/* Summary of a fused list: number of fused gates, sum of their op counts
+ * (2 per nonzero real matrix scalar, Sec. III-C), and host fusion time. */
+cast_status fused_info(const cast_fused *f, size_t *n_fused, double *total_opcount,
+                       double *fusion_ms);
+
+/* Details of fused gate i: its k, sorted qubits (6 ints), op count, the
+ * dimension d of the XOR subspace spanned by its nonzero pattern and the
+ * number of non-identity blocks.  `matrix` (NULL or 2 * 4^k doubles) receives
+ * its FP64 matrix with bit i <-> sorted qubit i.  For tests and reports. */
+cast_status fused_gate(const cast_fused *f, size_t i, int *k, int *qubits, double *opcount,
+                       int *subspace_dim, int *active_blocks, double *matrix);
+
+/* Applies every fused gate, in order, to the state (one device pass each).
+ * The state's n must equal the n given to fuse_circuit.  Queued on the
+ * state's stream. */
+cast_status apply_circuit(cast_sv *sv, const cast_fused *f);
+
+/* Frees a fused list.  NULL-safe.  The caller must not destroy a list while
+ * work that uses it is still queued (synchronise the stream first). */
+void fused_destroy(cast_fused *f);
+
+/* ------------------------------------------------------------ observables */
+
+/* A Pauli term coeff * P with P = i^{|x & z|} X^x Z^z: bit q of xmask/zmask
+ * gives qubit q's letter (x,z) = (1,0) X, (1,1) Y, (0,1) Z. */
+typedef struct {
+    double coeff;
+    uint64_t xmask;
+    uint64_t zmask;
+} cast_pauli_term;
+
+/* out[0] = sum_m coeff_m <psi|P_m|psi> (real part) and out[1] its imaginary
+ * part (round-off for Hermitian sums), accumulated in FP64 for both dtypes
+ * with a fixed reduction order.  Synchronous. */
+cast_status expval(const cast_sv *sv, const cast_pauli_term *terms, size_t n_terms, double *out);
+
+/* ------------------------------------------------------------ gradients */
+
+/* Energy and adjoint-method gradient (Jones & Gacon 2020) of
+ * E(theta) = <psi(theta)|H|psi(theta)>, psi(theta) = U_L ... U_1 |init>.
+ * `init` is copied, not modified; the work uses the init state's dtype and
+ * stream.  grad has n_params entries.  Synchronous. */
+cast_status adjoint_grad(const cast_sv *init, const cast_gate *gates, size_t n_gates,
+                         const double *theta, size_t n_params,
+                         const cast_pauli_term *terms, size_t n_terms,
+                         double *energy, double *grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAST_H */

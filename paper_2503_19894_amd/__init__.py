@@ -1,0 +1,300 @@
+"""Python binding of libcast, the MI355X fused-gate state-vector engine.
+
+Argument marshalling only: every step of the simulation runs in the library's
+HIP kernels.  The raw C entry points are re-exported under their C names
+(``sv_create``, ``apply_gate``, ``fuse_circuit``, ``apply_circuit``,
+``expval``, ``adjoint_grad``, ...), raising :class:`CastError` on a non-zero
+status.  On top sit small conveniences: :class:`StateVector` (a torch tensor
+on the GPU wrapped with ``sv_wrap``), :func:`fuse` (gate records ->
+fused list) and :class:`CircuitEnergy` (``torch.autograd.Function`` whose
+backward returns adjoint gradients).
+
+Importing this package without the built library raises ImportError: there is
+no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime libcast binds to (one runtime per process)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcast.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2503_19894_amd/build.py` "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+C64, C128 = 1, 2
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class cast_gate(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("qubits", ctypes.c_int * 6), ("matrix", _c_double_p),
+                ("param_id", ctypes.c_int), ("param_coeff", ctypes.c_double), ("generator", ctypes.c_int)]
+
+
+class cast_fusion_opts(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int), ("opcount_cap", ctypes.c_double), ("zero_tol", ctypes.c_double),
+                ("one_tol", ctypes.c_double), ("agglomerative", ctypes.c_int), ("multi_traversal", ctypes.c_int),
+                ("cost_model", ctypes.c_int)]
+
+
+class cast_pauli_term(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("xmask", ctypes.c_uint64), ("zmask", ctypes.c_uint64)]
+
+
+#: exported symbol -> (restype, argtypes); the same list tests check against include/cast.h
+SIGNATURES = {
+    "cast_last_error": (ctypes.c_char_p, []),
+    "sv_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sv_wrap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]),
+    "sv_destroy": (None, [ctypes.c_void_p]),
+    "sv_copy_from_host": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sv_copy_to_host": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "sv_set_basis": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "sv_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p, _c_int_p]),
+    "apply_gate": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.c_int, _c_double_p]),
+    "gate_matrix": (ctypes.c_int, [ctypes.c_char_p, _c_double_p, _c_int_p, _c_double_p]),
+    "fusion_opts_default": (None, [ctypes.POINTER(cast_fusion_opts)]),
+    "fuse_circuit": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(cast_gate), ctypes.c_size_t,
+                                    ctypes.POINTER(cast_fusion_opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "fused_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t), _c_double_p, _c_double_p]),
+    "fused_gate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, _c_int_p, _c_int_p, _c_double_p, _c_int_p,
+                                  _c_int_p, _c_double_p]),
+    "apply_circuit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fused_destroy": (None, [ctypes.c_void_p]),
+    "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
+    "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
+                                    ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
+                                    _c_double_p, _c_double_p]),
+}
+
+for _name, (_res, _args) in SIGNATURES.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class CastError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcast error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise CastError(rc, _lib.cast_last_error().decode())
+    return rc
+
+
+def _raw(name):
+    f = getattr(_lib, name)
+
+    def call(*args):
+        r = f(*args)
+        if SIGNATURES[name][0] is ctypes.c_int:
+            _check(r)
+        return r
+
+    call.__name__ = name
+    return call
+
+
+# raw C entry points under their C names
+for _name in SIGNATURES:
+    if _name != "cast_last_error":
+        globals()[_name] = _raw(_name)
+last_error = lambda: _lib.cast_last_error().decode()  # noqa: E731
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_c_double_p)
+
+
+# --------------------------------------------------------------------- gates
+#: Pauli letter codes of the rotation generators (2 bits per qubit)
+_GEN = {"rx": 1, "ry": 2, "rz": 3, "rxx": 1 | (1 << 2), "ryy": 2 | (2 << 2), "rzz": 3 | (3 << 2)}
+
+
+def std_matrix(name, params=()):
+    """Matrix of a standard gate, built by the library (interleaved float64
+    array of shape (2^k, 2^k, 2))."""
+    p = np.zeros(3)
+    p[:len(params)] = params
+    out = np.zeros(2 * 64 * 64)
+    k = ctypes.c_int()
+    gate_matrix(name.encode(), _dptr(p), ctypes.byref(k), _dptr(out))
+    D = 1 << k.value
+    return out[:2 * D * D].reshape(D, D, 2).copy()
+
+
+class GateArray:
+    """cast_gate[] for a list of gate records (keeps matrices alive)."""
+
+    def __init__(self, gates):
+        self.arr = (cast_gate * max(1, len(gates)))()
+        self._keep = []
+        for i, g in enumerate(gates):
+            cg = self.arr[i]
+            cg.k = len(g.qubits)
+            for j, q in enumerate(g.qubits):
+                cg.qubits[j] = int(q)
+            cg.param_id = int(getattr(g, "param", -1))
+            cg.param_coeff = float(getattr(g, "coeff", 1.0))
+            if cg.param_id >= 0:
+                cg.generator = _GEN[g.name]
+                cg.matrix = None
+            else:
+                cg.generator = 0
+                if g.name == "unitary":
+                    m = np.ascontiguousarray(np.asarray(g.matrix, dtype=np.complex128)).view(np.float64).copy()
+                else:
+                    m = np.ascontiguousarray(std_matrix(g.name, g.params)).reshape(-1)
+                self._keep.append(m)
+                cg.matrix = _dptr(m)
+        self.n = len(gates)
+
+
+def pauli_terms(terms):
+    """cast_pauli_term[] from records with .coeff and .ops = ((qubit, 'X'|'Y'|'Z'), ...)."""
+    arr = (cast_pauli_term * max(1, len(terms)))()
+    for i, t in enumerate(terms):
+        x = z = 0
+        for q, p in t.ops:
+            if p in "XY":
+                x |= 1 << q
+            if p in "YZ":
+                z |= 1 << q
+        arr[i].coeff = float(t.coeff)
+        arr[i].xmask = x
+        arr[i].zmask = z
+    return arr
+
+
+def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, agglomerative=True,
+                   multi_traversal=True, cost_model=0):
+    o = cast_fusion_opts()
+    o.k_max, o.opcount_cap, o.zero_tol, o.one_tol = k_max, opcount_cap, zero_tol, one_tol
+    o.agglomerative, o.multi_traversal, o.cost_model = int(agglomerative), int(multi_traversal), cost_model
+    return o
+
+
+class FusedCircuit:
+    """A fused gate list owned by the library."""
+
+    def __init__(self, n, gates, **opts):
+        ga = GateArray(gates)
+        o = fusion_options(**opts)
+        h = ctypes.c_void_p()
+        fuse_circuit(n, ga.arr, ga.n, ctypes.byref(o), ctypes.byref(h))
+        self.handle = h
+        self.n = n
+
+    def info(self):
+        nf, oc, ms = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_double()
+        fused_info(self.handle, ctypes.byref(nf), ctypes.byref(oc), ctypes.byref(ms))
+        return {"n_fused": nf.value, "opcount": oc.value, "fusion_ms": ms.value}
+
+    def gate(self, i, with_matrix=False):
+        k, d, nb, oc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        qs = (ctypes.c_int * 6)()
+        m = np.zeros(2 * 64 * 64) if with_matrix else None
+        fused_gate(self.handle, i, ctypes.byref(k), qs, ctypes.byref(oc), ctypes.byref(d), ctypes.byref(nb),
+                   _dptr(m) if with_matrix else None)
+        out = {"k": k.value, "qubits": tuple(qs[:k.value]), "opcount": oc.value, "d": d.value,
+               "active_blocks": nb.value}
+        if with_matrix:
+            D = 1 << k.value
+            out["matrix"] = m[:2 * D * D].view(np.complex128).reshape(D, D)
+        return out
+
+    def __len__(self):
+        return self.info()["n_fused"]
+
+    def __del__(self, _destroy=_lib.fused_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+
+# --------------------------------------------------------------------- states
+class StateVector:
+    """A 2^n state in a torch tensor (complex64 / complex128 on a GPU),
+    wrapped for the library on the tensor's current stream."""
+
+    def __init__(self, n, dtype=torch.complex128, device="cuda", tensor=None):
+        if tensor is None:
+            tensor = torch.zeros(1 << n, dtype=dtype, device=device)
+            tensor[0] = 1
+        assert tensor.is_cuda and tensor.is_contiguous() and tensor.numel() == 1 << n
+        assert tensor.dtype in (torch.complex64, torch.complex128)
+        self.tensor = tensor
+        self.n = n
+        self.dt = C128 if tensor.dtype == torch.complex128 else C64
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(tensor.device).cuda_stream
+        sv_wrap(ctypes.c_void_p(tensor.data_ptr()), n, self.dt, ctypes.c_void_p(stream), ctypes.byref(h))
+        self.handle = h
+
+    def apply_gate(self, qubits, matrix):
+        m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex128)).view(np.float64)
+        q = (ctypes.c_int * len(qubits))(*[int(x) for x in qubits])
+        apply_gate(self.handle, q, len(qubits), _dptr(m))
+
+    def apply_circuit(self, fused: FusedCircuit):
+        apply_circuit(self.handle, fused.handle)
+
+    def expval(self, terms):
+        arr = pauli_terms(terms)
+        out = np.zeros(2)
+        expval(self.handle, arr, len(terms), _dptr(out))
+        return complex(out[0], out[1])
+
+    def numpy(self):
+        torch.cuda.current_stream(self.tensor.device).synchronize()
+        return self.tensor.cpu().numpy()
+
+    def __del__(self, _destroy=_lib.sv_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+
+def adjoint(init: StateVector, gates, theta, terms):
+    """(energy, gradient) of <psi(theta)|H|psi(theta)> by the adjoint method."""
+    ga = GateArray(gates)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    grad = np.zeros(max(1, th.size))
+    e = ctypes.c_double()
+    arr = pauli_terms(terms)
+    adjoint_grad(init.handle, ga.arr, ga.n, _dptr(th), th.size, arr, len(terms), ctypes.byref(e), _dptr(grad))
+    return e.value, grad[:th.size].copy()
+
+
+class CircuitEnergy(torch.autograd.Function):
+    """E[b] = <psi(theta_b)|H|psi(theta_b)> for theta of shape [B, P] (or [P]);
+    backward returns grad_out[b] * dE[b]/dtheta_b from the adjoint sweep done
+    in forward."""
+
+    @staticmethod
+    def forward(ctx, theta, n, gates, terms, dtype=torch.complex128):
+        th = theta.detach().to("cpu", torch.float64)
+        flat = th.reshape(-1, th.shape[-1])
+        init = StateVector(n, dtype=dtype)
+        es, gs = [], []
+        for row in flat.numpy():
+            e, g = adjoint(init, gates, row, terms)
+            es.append(e)
+            gs.append(g)
+        ctx.save_for_backward(torch.tensor(np.array(gs), dtype=theta.dtype).reshape(theta.shape))
+        return torch.tensor(es, dtype=theta.dtype).reshape(theta.shape[:-1]).to(theta.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out.to(g.device).unsqueeze(-1) * g, None, None, None, None

@@ -1,0 +1,453 @@
+// C ABI of libcast (declared in include/cast.h): argument validation, state
+// objects, host->device matrix staging, and the host side of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "internal.hpp"
+
+namespace cast {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+cast_status fail(cast_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+Tuning &tuning() {
+    static Tuning t = [] {
+        Tuning x;
+        // environment overrides for sweeps: CAST_DIRECT_MIN_Q_C64/C128, CAST_TILE_BITS_C64/C128
+        auto env = [](const char *name, int &v) {
+            if (const char *s = std::getenv(name)) v = std::atoi(s);
+        };
+        env("CAST_DIRECT_MIN_Q_C64", x.direct_min_q[CAST_C64]);
+        env("CAST_DIRECT_MIN_Q_C128", x.direct_min_q[CAST_C128]);
+        env("CAST_TILE_BITS_C64", x.tile_bits[CAST_C64]);
+        env("CAST_TILE_BITS_C128", x.tile_bits[CAST_C128]);
+        env("CAST_MAX_GRID", x.max_grid);
+        return x;
+    }();
+    return t;
+}
+
+// ----------------------------------------------------------------- memory
+static std::mutex g_mem_mu;
+static size_t g_mem_used = 0;
+
+static size_t mem_cap() {
+    static size_t cap = [] {
+        const char *s = std::getenv("CAST_MAX_DEVICE_BYTES");
+        return s ? (size_t)std::strtoull(s, nullptr, 10) : (size_t)0;
+    }();
+    return cap;
+}
+
+static std::mutex g_size_mu;
+static std::vector<std::pair<void *, size_t>> g_sizes;
+
+cast_status dev_alloc(void **ptr, size_t bytes) {
+    *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        if (mem_cap() && g_mem_used + bytes > mem_cap())
+            return fail(CAST_ENOMEM, "allocation of " + std::to_string(bytes) +
+                                         " bytes exceeds CAST_MAX_DEVICE_BYTES");
+        g_mem_used += bytes;
+    }
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        g_mem_used -= bytes;
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? CAST_ENOMEM : CAST_EHIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    std::lock_guard<std::mutex> lk(g_size_mu);
+    g_sizes.emplace_back(*ptr, bytes);
+    return CAST_OK;
+}
+
+void dev_free(void *ptr) {
+    if (!ptr) return;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_size_mu);
+        for (size_t i = 0; i < g_sizes.size(); ++i)
+            if (g_sizes[i].first == ptr) {
+                bytes = g_sizes[i].second;
+                g_sizes[i] = g_sizes.back();
+                g_sizes.pop_back();
+                break;
+            }
+    }
+    (void)hipFree(ptr);
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_used -= bytes;
+}
+
+// ----------------------------------------------------------------- uploads
+template <typename R>
+static void pack(const PassPlan &p, std::vector<R> &dst) {
+    for (const cplx &z : p.mat) {
+        dst.push_back((R)z.real());
+        dst.push_back((R)z.imag());
+    }
+}
+
+cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
+                         std::vector<size_t> *offsets) {
+    offsets->clear();
+    std::vector<double> hd;
+    std::vector<float> hf;
+    size_t elems = 0;
+    for (const PassPlan &p : ps) {
+        offsets->push_back(elems);  // in reals of the dtype
+        if (dt == CAST_C128) pack<double>(p, hd), elems = hd.size();
+        else pack<float>(p, hf), elems = hf.size();
+        // keep every plan's matrices 256-byte aligned for scalar loads
+        const size_t align = 256 / (dt == CAST_C128 ? 8 : 4);
+        while (elems % align) {
+            if (dt == CAST_C128) hd.push_back(0); else hf.push_back(0);
+            ++elems;
+        }
+    }
+    const size_t bytes = elems * (dt == CAST_C128 ? 8 : 4);
+    cast_status st = dev_alloc(&out->ptr, bytes);
+    if (st) return st;
+    out->bytes = bytes;
+    if (bytes) {
+        hipError_t e = hipMemcpy(out->ptr, dt == CAST_C128 ? (void *)hd.data() : (void *)hf.data(), bytes,
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            dev_free(out->ptr);
+            out->ptr = nullptr;
+            return fail(CAST_EHIP, std::string("matrix upload: ") + hipGetErrorString(e));
+        }
+    }
+    return CAST_OK;
+}
+
+cast_status upload_plan(const PassPlan &p, cast_dtype dt, DeviceMatrix *out) {
+    std::vector<size_t> off;
+    return upload_plans(std::vector<PassPlan>{p}, dt, out, &off);
+}
+
+// Small per-thread cache of matrix buffers for apply_gate: a buffer is reused
+// only after the stream that used it has passed an event recorded after use.
+struct Staging {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+static std::mutex g_stage_mu;
+static std::vector<Staging> g_stage;
+
+static cast_status stage_matrix(const PassPlan &p, cast_dtype dt, hipStream_t s, void **dptr,
+                                hipEvent_t *ev) {
+    std::vector<double> hd;
+    std::vector<float> hf;
+    size_t bytes;
+    const void *src;
+    if (dt == CAST_C128) { pack<double>(p, hd); bytes = hd.size() * 8; src = hd.data(); }
+    else { pack<float>(p, hf); bytes = hf.size() * 4; src = hf.data(); }
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging *slot = nullptr;
+    for (Staging &st : g_stage)
+        if (st.bytes >= bytes && hipEventQuery(st.done) == hipSuccess) { slot = &st; break; }
+    if (!slot) {
+        Staging st;
+        st.bytes = std::max<size_t>(bytes, 4096);
+        cast_status rc = dev_alloc(&st.ptr, st.bytes);
+        if (rc) return rc;
+        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+            dev_free(st.ptr);
+            return fail(CAST_EHIP, "hipEventCreate failed");
+        }
+        g_stage.push_back(st);
+        slot = &g_stage.back();
+    }
+    // stream-ordered copy from pageable memory completes the host read before returning
+    CAST_HIP_TRY(hipMemcpyAsync(slot->ptr, src, bytes, hipMemcpyHostToDevice, s));
+    CAST_HIP_TRY(hipStreamSynchronize(s));
+    *dptr = slot->ptr;
+    *ev = slot->done;
+    return CAST_OK;
+}
+
+static cast_status check_sv(const cast_sv *sv) {
+    if (!sv) return fail(CAST_EINVAL, "state is NULL");
+    if (!sv->data) return fail(CAST_ESTATE, "state has no device memory");
+    return CAST_OK;
+}
+
+static cast_status check_qubits(int n, const int *qubits, int k) {
+    if (k < 1 || k > kMaxK) return fail(CAST_EINVAL, "k must be in [1, 6], got " + std::to_string(k));
+    if (!qubits) return fail(CAST_EINVAL, "qubits is NULL");
+    if (k > n) return fail(CAST_EINVAL, "gate has more qubits than the state");
+    for (int i = 0; i < k; ++i) {
+        if (qubits[i] < 0 || qubits[i] >= n)
+            return fail(CAST_EINVAL, "qubit " + std::to_string(qubits[i]) + " out of range");
+        for (int j = 0; j < i; ++j)
+            if (qubits[j] == qubits[i]) return fail(CAST_EINVAL, "duplicate qubit " + std::to_string(qubits[i]));
+    }
+    return CAST_OK;
+}
+
+static std::vector<cplx> read_matrix(int k, const double *m) {
+    const size_t D = (size_t)1 << k;
+    std::vector<cplx> out(D * D);
+    for (size_t i = 0; i < D * D; ++i) out[i] = cplx(m[2 * i], m[2 * i + 1]);
+    return out;
+}
+
+}  // namespace cast
+
+using namespace cast;
+
+extern "C" {
+
+const char *cast_last_error(void) { return g_err.c_str(); }
+
+// ----------------------------------------------------------------- states
+cast_status sv_create(int n, cast_dtype dt, void *hip_stream, cast_sv **out) {
+    if (!out) return fail(CAST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > kMaxQubits) return fail(CAST_EINVAL, "n must be in [1, 34]");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "dtype must be CAST_C64 or CAST_C128");
+    const size_t bytes = ((size_t)1 << n) * amp_bytes(dt);
+    void *p = nullptr;
+    cast_status rc = dev_alloc(&p, bytes);
+    if (rc) return rc;
+    cast_sv *sv = new cast_sv;
+    sv->data = p;
+    sv->n = n;
+    sv->dt = dt;
+    sv->stream = (hipStream_t)hip_stream;
+    sv->owns = true;
+    rc = sv_set_basis(sv, 0);
+    if (rc) {
+        sv_destroy(sv);
+        return rc;
+    }
+    *out = sv;
+    return CAST_OK;
+}
+
+cast_status sv_wrap(void *dev_ptr, int n, cast_dtype dt, void *hip_stream, cast_sv **out) {
+    if (!out) return fail(CAST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!dev_ptr) return fail(CAST_EINVAL, "dev_ptr is NULL");
+    if (((uintptr_t)dev_ptr) & 15) return fail(CAST_EINVAL, "dev_ptr must be 16-byte aligned");
+    if (n < 1 || n > kMaxQubits) return fail(CAST_EINVAL, "n must be in [1, 34]");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "dtype must be CAST_C64 or CAST_C128");
+    cast_sv *sv = new cast_sv;
+    sv->data = dev_ptr;
+    sv->n = n;
+    sv->dt = dt;
+    sv->stream = (hipStream_t)hip_stream;
+    sv->owns = false;
+    *out = sv;
+    return CAST_OK;
+}
+
+void sv_destroy(cast_sv *sv) {
+    if (!sv) return;
+    if (sv->owns && sv->data) {
+        (void)hipStreamSynchronize(sv->stream);
+        dev_free(sv->data);
+    }
+    sv->data = nullptr;
+    delete sv;
+}
+
+cast_status sv_copy_from_host(cast_sv *sv, const void *host, size_t bytes) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (!host) return fail(CAST_EINVAL, "host is NULL");
+    if (bytes != ((size_t)1 << sv->n) * amp_bytes(sv->dt)) return fail(CAST_EINVAL, "byte count mismatch");
+    CAST_HIP_TRY(hipMemcpyAsync(sv->data, host, bytes, hipMemcpyHostToDevice, sv->stream));
+    CAST_HIP_TRY(hipStreamSynchronize(sv->stream));
+    return CAST_OK;
+}
+
+cast_status sv_copy_to_host(const cast_sv *sv, void *host, size_t bytes) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (!host) return fail(CAST_EINVAL, "host is NULL");
+    if (bytes != ((size_t)1 << sv->n) * amp_bytes(sv->dt)) return fail(CAST_EINVAL, "byte count mismatch");
+    CAST_HIP_TRY(hipMemcpyAsync(host, sv->data, bytes, hipMemcpyDeviceToHost, sv->stream));
+    CAST_HIP_TRY(hipStreamSynchronize(sv->stream));
+    return CAST_OK;
+}
+
+cast_status sv_set_basis(cast_sv *sv, uint64_t index) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (sv->n < 64 && index >= ((uint64_t)1 << sv->n)) return fail(CAST_EINVAL, "basis index out of range");
+    const size_t ab = amp_bytes(sv->dt);
+    CAST_HIP_TRY(hipMemsetAsync(sv->data, 0, ((size_t)1 << sv->n) * ab, sv->stream));
+    static const double one_d[2] = {1.0, 0.0};
+    static const float one_f[2] = {1.0f, 0.0f};
+    CAST_HIP_TRY(hipMemcpyAsync((char *)sv->data + index * ab, sv->dt == CAST_C128 ? (const void *)one_d
+                                                                                   : (const void *)one_f,
+                                ab, hipMemcpyHostToDevice, sv->stream));
+    CAST_HIP_TRY(hipStreamSynchronize(sv->stream));
+    return CAST_OK;
+}
+
+cast_status sv_info(const cast_sv *sv, void **dev_ptr, int *n, cast_dtype *dt) {
+    if (!sv) return fail(CAST_EINVAL, "state is NULL");
+    if (dev_ptr) *dev_ptr = sv->data;
+    if (n) *n = sv->n;
+    if (dt) *dt = sv->dt;
+    return CAST_OK;
+}
+
+// ----------------------------------------------------------------- gates
+cast_status apply_gate(cast_sv *sv, const int *qubits, int k, const double *matrix) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (cast_status rc = check_qubits(sv->n, qubits, k)) return rc;
+    if (!matrix) return fail(CAST_EINVAL, "matrix is NULL");
+    std::vector<cplx> m = read_matrix(k, matrix);
+    PassPlan p;
+    if (cast_status rc = make_plan(k, qubits, m.data(), 1e-14, 1e-14, &p)) return rc;
+    if (p.identity()) return CAST_OK;
+    void *dmat = nullptr;
+    hipEvent_t ev = nullptr;
+    if (cast_status rc = stage_matrix(p, sv->dt, sv->stream, &dmat, &ev)) return rc;
+    cast_status rc = launch_pass(sv->data, sv->n, sv->dt, p, dmat, sv->stream);
+    CAST_HIP_TRY(hipEventRecord(ev, sv->stream));
+    return rc;
+}
+
+cast_status gate_matrix(const char *name, const double *params, int *k, double *out) {
+    if (!name || !k || !out) return fail(CAST_EINVAL, "NULL argument");
+    static const double zeros[3] = {0, 0, 0};
+    std::vector<cplx> m;
+    if (!standard_gate(name, params ? params : zeros, k, &m))
+        return fail(CAST_EINVAL, std::string("unknown gate ") + name);
+    for (size_t i = 0; i < m.size(); ++i) {
+        out[2 * i] = m[i].real();
+        out[2 * i + 1] = m[i].imag();
+    }
+    return CAST_OK;
+}
+
+void fusion_opts_default(cast_fusion_opts *o) {
+    if (!o) return;
+    o->k_max = 5;
+    o->opcount_cap = 0;
+    o->zero_tol = 1e-14;
+    o->one_tol = 1e-14;
+    o->agglomerative = 1;
+    o->multi_traversal = 1;
+    o->cost_model = 0;
+}
+
+cast_status fuse_circuit(int n, const cast_gate *gates, size_t n_gates, const cast_fusion_opts *opts,
+                         cast_fused **out) {
+    if (!out) return fail(CAST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > kMaxQubits) return fail(CAST_EINVAL, "n must be in [1, 34]");
+    if (n_gates && !gates) return fail(CAST_EINVAL, "gates is NULL");
+    cast_fusion_opts o;
+    fusion_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.k_max < 1 || o.k_max > kMaxK) return fail(CAST_EINVAL, "k_max must be in [1, 6]");
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<FusionGate> in;
+    in.reserve(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) {
+        const cast_gate &g = gates[i];
+        if (cast_status rc = check_qubits(n, g.qubits, g.k)) return rc;
+        if (g.param_id >= 0 || !g.matrix)
+            return fail(CAST_EINVAL, "fuse_circuit takes fixed gates (matrix set, param_id = -1)");
+        // sort the gate's qubits, permuting its matrix
+        PassPlan p;
+        std::vector<cplx> m = read_matrix(g.k, g.matrix);
+        if (cast_status rc = make_plan(g.k, g.qubits, m.data(), 0.0, 0.0, &p)) return rc;
+        FusionGate fg;
+        fg.qubits.assign(p.q, p.q + g.k);
+        fg.m = p.full;
+        in.push_back(std::move(fg));
+    }
+    std::vector<FusionGate> fused;
+    if (cast_status rc = fuse(n, std::move(in), o, &fused)) return rc;
+    cast_fused *f = new cast_fused;
+    f->n = n;
+    for (const FusionGate &g : fused) {
+        PassPlan p;
+        if (cast_status rc = make_plan((int)g.qubits.size(), g.qubits.data(), g.m.data(), o.zero_tol,
+                                       o.one_tol, &p)) {
+            delete f;
+            return rc;
+        }
+        f->plans.push_back(std::move(p));
+    }
+    f->fusion_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = f;
+    return CAST_OK;
+}
+
+cast_status fused_info(const cast_fused *f, size_t *n_fused, double *total_opcount, double *fusion_ms) {
+    if (!f) return fail(CAST_EINVAL, "fused list is NULL");
+    if (n_fused) *n_fused = f->plans.size();
+    if (total_opcount) {
+        double s = 0;
+        for (const PassPlan &p : f->plans) s += p.opcount;
+        *total_opcount = s;
+    }
+    if (fusion_ms) *fusion_ms = f->fusion_ms;
+    return CAST_OK;
+}
+
+cast_status fused_gate(const cast_fused *f, size_t i, int *k, int *qubits, double *opcount, int *subspace_dim,
+                       int *active_blocks, double *matrix) {
+    if (!f) return fail(CAST_EINVAL, "fused list is NULL");
+    if (i >= f->plans.size()) return fail(CAST_EINVAL, "index out of range");
+    const PassPlan &p = f->plans[i];
+    if (k) *k = p.k;
+    if (qubits)
+        for (int j = 0; j < kMaxK; ++j) qubits[j] = j < p.k ? p.q[j] : -1;
+    if (opcount) *opcount = p.opcount;
+    if (subspace_dim) *subspace_dim = p.d;
+    if (active_blocks) *active_blocks = (int)p.blk.size();
+    if (matrix)
+        for (size_t j = 0; j < p.full.size(); ++j) {
+            matrix[2 * j] = p.full[j].real();
+            matrix[2 * j + 1] = p.full[j].imag();
+        }
+    return CAST_OK;
+}
+
+cast_status apply_circuit(cast_sv *sv, const cast_fused *fc) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (!fc) return fail(CAST_EINVAL, "fused list is NULL");
+    if (fc->n != sv->n) return fail(CAST_EINVAL, "fused list was built for a different qubit count");
+    cast_fused *f = const_cast<cast_fused *>(fc);
+    const int dt = sv->dt;
+    if (!f->dev[dt].ptr && !f->plans.empty()) {
+        if (cast_status rc = upload_plans(f->plans, sv->dt, &f->dev[dt], &f->dev_off[dt])) return rc;
+    }
+    const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
+    for (size_t i = 0; i < f->plans.size(); ++i) {
+        const void *dm = (const char *)f->dev[dt].ptr + f->dev_off[dt][i] * rsz;
+        if (cast_status rc = launch_pass(sv->data, sv->n, sv->dt, f->plans[i], dm, sv->stream)) return rc;
+    }
+    return CAST_OK;
+}
+
+void fused_destroy(cast_fused *f) {
+    if (!f) return;
+    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr);
+    delete f;
+}
+
+}  // extern "C"

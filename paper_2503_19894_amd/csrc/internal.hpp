@@ -1,0 +1,121 @@
+// Internal declarations shared by the host sources of libcast.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cast.h"
+
+namespace cast {
+
+using cplx = std::complex<double>;
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+cast_status fail(cast_status code, const std::string &msg);
+
+#define CAST_HIP_TRY(expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::cast::fail(CAST_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------------- limits
+constexpr int kMaxQubits = 34;
+constexpr int kMaxK = 6;
+
+inline size_t amp_bytes(cast_dtype dt) { return dt == CAST_C128 ? 16 : 8; }
+
+// ----------------------------------------------------------------- pass plan
+// One device pass of a k-qubit gate.  Targets are sorted; the local (group
+// member) index j has bit i <-> q[i].  The matrix's nonzero pattern spans an
+// XOR subspace V of local indices; `L` is an invertible GF(2) relabelling
+// whose first d columns span V, so that in virtual coordinates u the matrix is
+// block-diagonal with 2^(k-d) dense blocks of 2^d x 2^d.  Identity blocks are
+// dropped from `blk`.
+struct PassPlan {
+    int k = 0;
+    int q[kMaxK] = {0};
+    int d = 0;
+    uint32_t L[kMaxK] = {0};        // physical local index of virtual basis vector i
+    std::vector<uint32_t> blk;      // active block ids b in [0, 2^(k-d))
+    std::vector<cplx> mat;          // blk.size() x 2^d x 2^d, row-major per block
+    std::vector<cplx> full;         // snapped FP64 matrix, bit i <-> q[i] (for reports)
+    double opcount = 0;             // 2 x nonzero real scalars (Sec. III-C)
+    bool identity() const { return blk.empty(); }
+};
+
+// Builds the plan of a gate given on (unsorted) qubits with bit i <-> qubits[i].
+cast_status make_plan(int k, const int *qubits, const cplx *m, double zero_tol, double one_tol,
+                      PassPlan *out);
+
+// Operation count of Sec. III-C: two operations per nonzero real scalar.
+double opcount_of(const std::vector<cplx> &m);
+
+// ----------------------------------------------------------------- device side
+struct DeviceMatrix {                // a plan's block matrices in the state dtype
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Tuning {                      // launch parameters chosen per (dtype, kernel)
+    int direct_min_q[3] = {0, 5, 4}; // smallest target for the direct kernel, by dtype
+    int tile_bits[3] = {0, 13, 12};  // LDS tile size log2(amplitudes), by dtype
+    int wg_direct = 256;
+    int wg_tile = 256;
+    int max_grid = 1 << 16;
+};
+Tuning &tuning();
+
+// Queues one pass on `stream`.  `dmat` holds the plan's blocks in dtype `dt`.
+cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
+                        hipStream_t stream);
+
+// Uploads a plan's matrices (cast to dt) into a new device buffer; the host
+// staging is synchronous (the buffer is ready when this returns).
+cast_status upload_plan(const PassPlan &p, cast_dtype dt, DeviceMatrix *out);
+cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
+                         std::vector<size_t> *offsets);
+
+// Device allocation with the CAST_MAX_DEVICE_BYTES cap.
+cast_status dev_alloc(void **ptr, size_t bytes);
+void dev_free(void *ptr);
+
+// ----------------------------------------------------------------- fusion
+struct FusionGate {                  // a gate as fusion sees it
+    std::vector<int> qubits;         // sorted
+    std::vector<cplx> m;             // bit i <-> qubits[i]
+};
+cast_status fuse(int n, std::vector<FusionGate> gates, const cast_fusion_opts &o,
+                 std::vector<FusionGate> *out);
+
+// Builds the matrix of a standard gate; returns false for unknown names.
+bool standard_gate(const std::string &name, const double *params, int *k, std::vector<cplx> *m);
+// exp(-i a G / 2) for a Pauli string G (letters in 2-bit fields, see cast.h).
+std::vector<cplx> rotation_matrix(int k, int generator, double angle);
+std::vector<cplx> pauli_string_matrix(int k, int generator);
+
+}  // namespace cast
+
+struct cast_sv {
+    void *data = nullptr;
+    int n = 0;
+    cast_dtype dt = CAST_C128;
+    hipStream_t stream = nullptr;
+    bool owns = false;
+};
+
+struct cast_fused {
+    int n = 0;
+    std::vector<cast::PassPlan> plans;
+    double fusion_ms = 0;
+    // device copies of the block matrices, per dtype (lazily uploaded)
+    cast::DeviceMatrix dev[3];
+    std::vector<size_t> dev_off[3];
+};

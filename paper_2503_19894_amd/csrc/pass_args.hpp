@@ -1,0 +1,25 @@
+// Kernel argument block of one gate pass (passed by value).
+#pragma once
+#include <cstdint>
+
+namespace cast {
+
+struct PassArgs {
+    uint64_t off[6];        // amplitude offset of each virtual basis vector
+    uint64_t lowmask[6];    // direct: (1 << q_i) - 1 for the sorted targets
+    uint64_t hilowmask[6];  // tile: (1 << qhi_j) - 1 for the high targets
+    uint64_t ngroups;       // direct: 2^(n-k)
+    uint64_t ntiles;        // tile: 2^(n-tb)
+    uint32_t tlowmask[6];   // tile: (1 << q_i) - 1 for the low targets
+    uint32_t toff[6];       // tile position of each virtual basis vector
+    uint32_t blk[64];       // active block ids
+    uint32_t nblk;
+    int k;
+    int log_ngroups;
+    int tb;                 // tile: log2(amplitudes per tile)
+    int W;                  // tile: contiguous window bits
+    int khi, klo;           // tile: targets at/above and below W
+    int qhi[6];             // tile: high targets, ascending
+};
+
+}  // namespace cast

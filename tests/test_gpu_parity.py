@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle,
+element by element, on the same seeded inputs.
+
+Bars: max |d amp| <= 1e-12 for complex128 and <= 1e-5 for complex64."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2503_19894_amd as cast  # noqa: E402
+from circuits import (Gate, PauliTerm, dense_haar_layers, gate_sweep, hea_vqa, qft, random_state,  # noqa: E402
+                      rqc_u3_cx, tfim_fields, tfim_trotter, vqa_hamiltonian, vqa_thetas)
+
+TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
+DTYPES = [torch.complex128, torch.complex64]
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(n, gates, psi0, dtype, k_max):
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+    fc = cast.FusedCircuit(n, gates, k_max=k_max)
+    sv.apply_circuit(fc)
+    return sv.numpy(), fc
+
+
+def maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a, dtype=np.complex128) - b)))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_config1_rqc12_unfused(dtype):
+    n = 12
+    gates = rqc_u3_cx(n, 10, seed=0)
+    want = oracle.run_circuit(n, gates)
+    psi0 = np.zeros(1 << n, dtype=np.complex128)
+    psi0[0] = 1
+    note("rqc12", dtype)
+    got, fc = run_gpu(n, gates, psi0, dtype, k_max=1)
+    assert len(fc) == 175
+    err = maxerr(got, want)
+    note("rqc12 err", err)
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_config1_apply_gate_one_by_one(dtype):
+    n = 12
+    gates = rqc_u3_cx(n, 10, seed=1)
+    want = oracle.run_circuit(n, gates)
+    sv = cast.StateVector(n, dtype=dtype)
+    for g in gates:
+        sv.apply_gate(g.qubits, oracle.gates.matrix(g))
+    assert maxerr(sv.numpy(), want) <= TOL[dtype]
+
+
+PLACEMENTS = {
+    "low": lambda n, k, rng: tuple(range(k)),
+    "high": lambda n, k, rng: tuple(range(n - k, n)),
+    "straddle": lambda n, k, rng: tuple(sorted(set([0, 3] + list(range(n - k + 2, n))))[:k]),
+    "random": lambda n, k, rng: tuple(int(x) for x in rng.permutation(n)[:k]),
+    "window": lambda n, k, rng: tuple(range(5, 5 + k)),
+}
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("kind", ["haar", "diag", "x", "ctrl", "h", "u3"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_single_pass_patterns(dtype, kind, k):
+    n = 17
+    rng = np.random.default_rng(100 * k + len(kind))
+    psi0 = random_state(n, seed=k, workload=9)
+    for pname, place in PLACEMENTS.items():
+        qs = place(n, k, rng)
+        if len(set(qs)) != k:
+            continue
+        gates = gate_sweep(kind, k, qs, seed=k)
+        note(f"pattern {kind} k={k} {pname} qubits={qs} {dtype}")
+        want = oracle.run_circuit(n, gates, psi0)
+        got, fc = run_gpu(n, gates, psi0, dtype, k_max=k)
+        # Alg. 1 fuses commuting blocks only in neighbouring qubit cells, so
+        # k one-qubit gates on scattered targets may stay several passes
+        assert 1 <= len(fc) <= len(gates)
+        err = maxerr(got, want)
+        assert err <= TOL[dtype], (pname, qs, err)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 9, 11])
+def test_small_states(dtype, n):
+    gates = rqc_u3_cx(n, 3, seed=n) + qft(n)
+    psi0 = random_state(n, seed=n, workload=9)
+    want = oracle.run_circuit(n, gates, psi0)
+    for k in sorted({1, min(n, 3), min(n, 6)}):
+        note(f"small n={n} k_max={k} {dtype}")
+        got, _ = run_gpu(n, gates, psi0, dtype, k_max=max(k, 2 if n >= 2 else 1))
+        assert maxerr(got, want) <= TOL[dtype]
+
+
+FUSED = {
+    "qft16": (16, lambda: qft(16)),
+    "haar16": (16, lambda: dense_haar_layers(16, depth=3, seed=0)),
+    "rqc15": (15, lambda: rqc_u3_cx(15, 8, seed=2)),
+}
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("case", sorted(FUSED))
+@pytest.mark.parametrize("k_max", [2, 3, 4, 5, 6])
+def test_fused_circuits(dtype, case, k_max):
+    n, mk = FUSED[case]
+    gates = mk()
+    k_max = max(k_max, max(g.k for g in gates))
+    psi0 = random_state(n, seed=5, workload=9)
+    want = oracle.run_circuit(n, gates, psi0)
+    note(f"fused {case} k_max={k_max} {dtype}")
+    got, fc = run_gpu(n, gates, psi0, dtype, k_max)
+    err = maxerr(got, want)
+    note(f"  passes={len(fc)} err={err:.2e}")
+    assert err <= TOL[dtype]
+
+
+def test_qft_closed_form_via_fft():
+    n = 20
+    psi0 = random_state(n, seed=3, workload=2)
+    want = np.fft.ifft(psi0) * math.sqrt(1 << n)
+    for dtype in DTYPES:
+        for k in (1, 3, 5):
+            note(f"qft20 k_max={k} {dtype}")
+            got, _ = run_gpu(n, qft(n), psi0, dtype, k)
+            assert maxerr(got, want) <= TOL[dtype]
+
+
+def test_bitwise_deterministic():
+    n = 18
+    psi0 = random_state(n, seed=1, workload=9)
+    gates = dense_haar_layers(17, depth=2, seed=1) + qft(17)
+    outs = []
+    for _ in range(2):
+        got, _ = run_gpu(17, gates, psi0[: 1 << 17] / np.linalg.norm(psi0[: 1 << 17]), torch.complex128, 5)
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_guard_region_untouched():
+    n = 16
+    buf = torch.full((3 << n,), 7.0 + 3.0j, dtype=torch.complex128, device="cuda")
+    psi0 = random_state(n, seed=2, workload=9)
+    mid = buf[1 << n: 2 << n]
+    mid.copy_(torch.tensor(psi0))
+    sv = cast.StateVector(n, tensor=mid)
+    fc = cast.FusedCircuit(n, dense_haar_layers(16, 2, seed=3), k_max=6)
+    sv.apply_circuit(fc)
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert np.all(h[: 1 << n] == 7.0 + 3.0j) and np.all(h[2 << n:] == 7.0 + 3.0j)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_expval(dtype):
+    n = 14
+    psi0 = random_state(n, seed=4, workload=9)
+    rng = np.random.default_rng(4)
+    terms = vqa_hamiltonian(n)
+    for _ in range(12):
+        qs = rng.permutation(n)[: rng.integers(1, 5)]
+        terms.append(PauliTerm(float(rng.normal()), tuple((int(q), "XYZ"[rng.integers(3)]) for q in qs)))
+    want = oracle.expval(psi0, terms)
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+    got = sv.expval(terms)
+    tol = 1e-12 if dtype == torch.complex128 else 1e-5 * sum(abs(t.coeff) for t in terms)
+    assert abs(got - want) <= tol, (got, want)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_adjoint_vs_oracle(dtype):
+    n = 8
+    gates, P = hea_vqa(n, 3)
+    theta = vqa_thetas(P, 2, seed=0)[1]
+    H = vqa_hamiltonian(n)
+    e_want, g_want = oracle.adjoint_grad(n, gates, theta, H)
+    init = cast.StateVector(n, dtype=dtype)
+    e, g = cast.adjoint(init, gates, theta, H)
+    tol = 1e-10 if dtype == torch.complex128 else 5e-4
+    note(f"adjoint {dtype}: dE={abs(e - e_want):.2e} dg={np.max(np.abs(g - g_want)):.2e}")
+    assert abs(e - e_want) <= tol
+    assert np.max(np.abs(g - g_want)) <= tol
+
+
+def test_adjoint_tfim_shared_params_and_symmetry():
+    n = 6
+    h = tfim_fields(n, seed=0)
+    psi0 = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    obs = [PauliTerm(1.0, ((0, "Z"),))]
+    for conv in ("xx", "zz"):
+        gates = tfim_trotter(n, steps=5, dt=0.05, convention=conv)
+        e_want, g_want = oracle.adjoint_grad(n, gates, h, obs, psi0)
+        init = cast.StateVector(n, tensor=torch.tensor(psi0, device="cuda"))
+        e, g = cast.adjoint(init, gates, h, obs)
+        assert abs(e - e_want) <= 1e-12 and np.max(np.abs(g - g_want)) <= 1e-12
+        if conv == "zz":
+            assert abs(e) <= 1e-12 and np.max(np.abs(g)) <= 1e-12
+
+
+def test_autograd_function():
+    n = 6
+    gates, P = hea_vqa(n, 2)
+    H = vqa_hamiltonian(n)
+    theta = torch.tensor(vqa_thetas(P, 3, seed=2), requires_grad=True)
+    E = cast.CircuitEnergy.apply(theta, n, gates, H)
+    w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)
+    (E.cpu() * w).sum().backward()
+    for b in range(3):
+        e_want, g_want = oracle.adjoint_grad(n, gates, theta[b].detach().numpy(), H)
+        assert abs(float(E[b]) - e_want) <= 1e-10
+        np.testing.assert_allclose(theta.grad[b].numpy(), w[b].item() * g_want, atol=1e-10)
