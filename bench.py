@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused-gate hot path on one MI355X.
+
+Workload: 30-qubit QFT (30 H + 435 controlled-phase + 15 SWAP gates) applied
+to a random normalised state with i.i.d. complex Gaussian amplitudes, after
+host fusion with k_max = 5.  One step = one application of the whole fused
+circuit (every fused gate = one in-place pass over the 2^30 amplitudes), with
+the state already resident in HBM.
+
+Headline value: effective HBM GB/s per fused-gate pass = passes x 2 x 2^30 x
+(amplitude bytes) / wall time of the timed steps (every amplitude read and
+written once per pass).  The line also carries:
+  roofline     -- the dominant kernel's algorithmic bytes (amplitudes of
+                  non-identity blocks, read + written) over its average launch
+                  duration from HIP events on the state's stream, vs 8 TB/s;
+  cpu_baseline -- the FP64 CPU oracle timed on a bounded sample of the same
+                  workload (the first unfused QFT gates on the same 2^30
+                  state), in the same unit;
+  extras       -- the complex64 run and per-kernel breakdowns.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+KERNEL_NAMES = {0: "k_direct", 1: "k_tile", 2: "k_tile"}
+
+
+def kernel_label(info, dtype_name):
+    kind = info["kernel"]
+    r = "double" if dtype_name == "c128" else "float"
+    if kind == 0:
+        return f"k_direct<{info['d']}, {r}, true>"
+    uni = "true"  # tiles hold >= 64 groups at n = 30
+    two = "true" if kind == 2 else "false"
+    return f"k_tile<{info['d']}, {r}, {uni}, {two}>"
+
+
+def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import qft, random_state_torch
+
+    dtype = torch.complex128 if dtype_name == "c128" else torch.complex64
+    amp = 16 if dtype_name == "c128" else 8
+    gates = qft(n)
+    t0 = time.perf_counter()
+    fc = cast.FusedCircuit(n, gates, k_max=k_max)
+    host_fusion_ms = (time.perf_counter() - t0) * 1e3
+    npass = len(fc)
+    infos = [fc.pass_info(i, dtype) for i in range(npass)]
+    psi = random_state_torch(n, seed=seed, device="cuda", dtype=dtype)
+    sv = cast.StateVector(n, tensor=psi)
+    for _ in range(warmup):
+        sv.apply_circuit(fc)
+    torch.cuda.synchronize()
+    per_pass = np.zeros(npass)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_pass += sv.apply_circuit_timed(fc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_pass /= steps
+    state_bytes = (1 << n) * amp
+    eff_gbs = npass * 2 * state_bytes * steps / wall / 1e9
+    # per-kernel totals from the HIP events
+    kern = {}
+    for inf, ms in zip(infos, per_pass):
+        if inf["kernel"] < 0:
+            continue
+        lab = kernel_label(inf, dtype_name)
+        k = kern.setdefault(lab, {"launches_per_step": 0, "ms_per_step": 0.0, "alg_bytes_per_step": 0.0,
+                                  "flops_per_step": 0.0})
+        k["launches_per_step"] += 1
+        k["ms_per_step"] += float(ms)
+        k["alg_bytes_per_step"] += inf["alg_bytes"]
+        k["flops_per_step"] += inf["flops"]
+    for k in kern.values():
+        k["avg_launch_ms"] = k["ms_per_step"] / k["launches_per_step"]
+        k["alg_bytes_per_launch"] = k["alg_bytes_per_step"] / k["launches_per_step"]
+        k["achieved_gbs"] = k["alg_bytes_per_step"] / (k["ms_per_step"] * 1e-3) / 1e9
+    dominant = max(kern, key=lambda x: kern[x]["ms_per_step"])
+    out = {
+        "passes": npass, "host_fusion_ms": round(host_fusion_ms, 2), "wall_s": wall,
+        "ms_per_step": wall / steps * 1e3, "effective_gbs": eff_gbs,
+        "paper_gibps_per_pass": state_bytes / (per_pass.sum() / npass * 1e-3) / 2**30,
+        "event_ms_per_step": float(per_pass.sum()),
+        "kernels": kern, "dominant": dominant,
+    }
+    del sv, psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n, target_s=15.0, max_gates=8):
+    """The oracle (FP64, OpenMP over groups) on the first unfused QFT gates of
+    a 2^n state; returns effective GB/s per pass in the same convention."""
+    import numpy as np
+
+    import oracle
+    from circuits import qft
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    N = 1 << n
+    psi = np.empty(N, dtype=np.complex128)
+    psi.real = 1.0 / math.sqrt(N)       # touch every page before timing
+    psi.imag = 0.0
+    gates = qft(n)
+    done, t_total = 0, 0.0
+    for g in gates[:max_gates]:
+        U = oracle.gates.matrix(g)
+        t0 = time.perf_counter()
+        oracle.apply_gate(psi, g.qubits, U)
+        t_total += time.perf_counter() - t0
+        done += 1
+        if t_total >= target_s:
+            break
+    gbs = done * 2 * N * 16 / t_total / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} unfused QFT-{n} gates on a 2^{n} FP64 state, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--k-max", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
+              "MI355X; runs on more than one GPU are not supported.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    main_run = run_gpu(args.n, args.k_max, "c128", args.steps, args.warmup)
+    extras = {}
+    if not args.no_c64:
+        extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup)
+    dom = main_run["kernels"][main_run["dominant"]]
+    roof = {"bound": "hbm", "kernel": main_run["dominant"], "achieved": round(dom["achieved_gbs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
+            "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
+    line = {
+        "metric": "effective HBM GB/s per fused-gate pass at 30q",
+        "value": round(main_run["effective_gbs"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"qft{args.n}_complex128_kmax{args.k_max}", "n_qubits": args.n,
+                   "k_max": args.k_max, "fused_passes": main_run["passes"],
+                   "state_bytes": (1 << args.n) * 16},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extras": {"c128": main_run, **extras},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

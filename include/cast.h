@@ -160,6 +160,19 @@ cast_status fused_gate(const cast_fused *f, size_t i, int *k, int *qubits, doubl
  * state's stream. */
 cast_status apply_circuit(cast_sv *sv, const cast_fused *f);
 
+/* Same as apply_circuit, but records a HIP event pair around every pass on
+ * the state's stream and returns each pass's device time in pass_ms (n_fused
+ * floats, milliseconds).  Synchronous.  For measurement. */
+cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *f, float *pass_ms);
+
+/* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct
+ * gather), 1 (LDS tile) or 2 (LDS tile, two buffers), *d the block dimension,
+ * and the pass's algorithmic HBM bytes (every amplitude of a non-identity
+ * block read once and written once) and flops (8 per complex multiply-add
+ * over the non-identity blocks). */
+cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt, int *kernel, int *d,
+                            double *alg_bytes, double *flops);
+
 /* Frees a fused list.  NULL-safe.  The caller must not destroy a list while
  * work that uses it is still queued (synchronise the stream first). */
 void fused_destroy(cast_fused *f);

@@ -68,6 +68,9 @@ SIGNATURES = {
                                   _c_int_p, _c_double_p]),
     "apply_circuit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fused_destroy": (None, [ctypes.c_void_p]),
+    "apply_circuit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "fused_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                       _c_int_p, _c_double_p, _c_double_p]),
     "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
                                     ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
@@ -213,6 +216,16 @@ class FusedCircuit:
             out["matrix"] = m[:2 * D * D].view(np.complex128).reshape(D, D)
         return out
 
+    def pass_info(self, i, dtype):
+        """Kernel choice and algorithmic bytes / flops of pass i on this
+        circuit's n qubits in `dtype` (torch complex dtype)."""
+        dt = C128 if dtype == torch.complex128 else C64
+        kern, d = ctypes.c_int(), ctypes.c_int()
+        b, f = ctypes.c_double(), ctypes.c_double()
+        fused_pass_info(self.handle, i, self.n, dt, ctypes.byref(kern), ctypes.byref(d), ctypes.byref(b),
+                        ctypes.byref(f))
+        return {"kernel": kern.value, "d": d.value, "alg_bytes": b.value, "flops": f.value}
+
     def __len__(self):
         return self.info()["n_fused"]
 
@@ -248,6 +261,13 @@ class StateVector:
 
     def apply_circuit(self, fused: FusedCircuit):
         apply_circuit(self.handle, fused.handle)
+
+    def apply_circuit_timed(self, fused: FusedCircuit):
+        """Applies the circuit and returns per-pass device times (ms)."""
+        nf = len(fused)
+        out = (ctypes.c_float * max(1, nf))()
+        apply_circuit_timed(self.handle, fused.handle, out)
+        return np.array(out[:nf], dtype=np.float64)
 
     def expval(self, terms):
         arr = pauli_terms(terms)

@@ -34,6 +34,8 @@ Tuning &tuning() {
         env("CAST_TILE_BITS_C64", x.tile_bits[CAST_C64]);
         env("CAST_TILE_BITS_C128", x.tile_bits[CAST_C128]);
         env("CAST_MAX_GRID", x.max_grid);
+        env("CAST_DIRECT_IPT", x.direct_ipt);
+        env("CAST_DIRECT_NT", x.direct_nt);
         return x;
     }();
     return t;
@@ -441,6 +443,49 @@ cast_status apply_circuit(cast_sv *sv, const cast_fused *fc) {
         const void *dm = (const char *)f->dev[dt].ptr + f->dev_off[dt][i] * rsz;
         if (cast_status rc = launch_pass(sv->data, sv->n, sv->dt, f->plans[i], dm, sv->stream)) return rc;
     }
+    return CAST_OK;
+}
+
+cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *fc, float *pass_ms) {
+    if (cast_status rc = check_sv(sv)) return rc;
+    if (!fc || !pass_ms) return fail(CAST_EINVAL, "NULL argument");
+    if (fc->n != sv->n) return fail(CAST_EINVAL, "fused list was built for a different qubit count");
+    cast_fused *f = const_cast<cast_fused *>(fc);
+    const int dt = sv->dt;
+    if (!f->dev[dt].ptr && !f->plans.empty()) {
+        if (cast_status rc = upload_plans(f->plans, sv->dt, &f->dev[dt], &f->dev_off[dt])) return rc;
+    }
+    const size_t np = f->plans.size();
+    std::vector<hipEvent_t> ev(np + 1);
+    for (auto &e : ev) CAST_HIP_TRY(hipEventCreate(&e));
+    const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
+    cast_status rc = CAST_OK;
+    CAST_HIP_TRY(hipEventRecord(ev[0], sv->stream));
+    for (size_t i = 0; i < np && !rc; ++i) {
+        const void *dm = (const char *)f->dev[dt].ptr + f->dev_off[dt][i] * rsz;
+        rc = launch_pass(sv->data, sv->n, sv->dt, f->plans[i], dm, sv->stream);
+        if (!rc) CAST_HIP_TRY(hipEventRecord(ev[i + 1], sv->stream));
+    }
+    if (!rc) {
+        CAST_HIP_TRY(hipEventSynchronize(ev[np]));
+        for (size_t i = 0; i < np; ++i) CAST_HIP_TRY(hipEventElapsedTime(&pass_ms[i], ev[i], ev[i + 1]));
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt, int *kernel, int *d,
+                            double *alg_bytes, double *flops) {
+    if (!f) return fail(CAST_EINVAL, "fused list is NULL");
+    if (i >= f->plans.size()) return fail(CAST_EINVAL, "index out of range");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n != f->n) return fail(CAST_EINVAL, "n differs from the fused list's");
+    const PassPlan &p = f->plans[i];
+    if (kernel) *kernel = p.identity() ? -1 : pass_kernel_kind(n, dt, p);
+    if (d) *d = p.d;
+    const double groups = std::ldexp(1.0, n - p.k), nb = (double)p.blk.size(), bd = std::ldexp(1.0, p.d);
+    if (alg_bytes) *alg_bytes = 2.0 * (double)amp_bytes(dt) * groups * nb * bd;
+    if (flops) *flops = 8.0 * groups * nb * bd * bd;
     return CAST_OK;
 }
 

@@ -60,39 +60,127 @@ __device__ __forceinline__ void cmac(V &acc, R mre, R mim, const V &v) {
 }
 
 // ------------------------------------------------------------------ direct
-template <int D, typename R, bool UNI>
+// IPT work items per thread per iteration, all loads issued before any
+// store.  NT: non-temporal hint on the state's loads and stores (the state is
+// streamed once per pass).
+typedef double native_d2 __attribute__((ext_vector_type(2)));
+typedef float native_f2 __attribute__((ext_vector_type(2)));
+template <typename V> struct Native;
+template <> struct Native<double2> { using T = native_d2; };
+template <> struct Native<float2> { using T = native_f2; };
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V *p) {
+    if (NT) {
+        const auto x = __builtin_nontemporal_load(reinterpret_cast<const typename Native<V>::T *>(p));
+        V v;
+        v.x = x.x;
+        v.y = x.y;
+        return v;
+    }
+    return *p;
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V *p, const V &v) {
+    if (NT) {
+        typename Native<V>::T x;
+        x.x = v.x;
+        x.y = v.y;
+        __builtin_nontemporal_store(x, reinterpret_cast<typename Native<V>::T *>(p));
+    } else {
+        *p = v;
+    }
+}
+
+template <int D, typename R, int IPT, bool NT>
 __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *__restrict__ mat,
                                                 PassArgs a) {
     using V = typename Amp<R>::T;
     constexpr int N = 1 << D;
     V *psi = reinterpret_cast<V *>(psi_r);
     const uint64_t items = a.ngroups * a.nblk;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += stride) {
-        uint32_t bs = (uint32_t)(i >> a.log_ngroups);
-        if (UNI) bs = __builtin_amdgcn_readfirstlane(bs);
+    constexpr uint64_t per_iter = 256ull * IPT;
+    const uint64_t nfull = items / per_iter;
+    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
+        uint64_t base[IPT];
+        const R *m[IPT];
+        V v[IPT][N];
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            const uint64_t i = it * per_iter + (uint64_t)u * 256 + threadIdx.x;
+            // every 64-lane slice lies inside one block's run of ngroups items
+            const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(i >> a.log_ngroups));
+            const uint64_t g = i & (a.ngroups - 1);
+            const uint32_t bid = a.blk[bs];
+            uint64_t b = deposit(g, a.lowmask, a.k);
+            for (int j = 0; j < a.k - D; ++j)
+                if ((bid >> j) & 1u) b ^= a.off[D + j];
+            base[u] = b;
+            m[u] = mat + (size_t)bs * (2 * N * N);
+#pragma unroll
+            for (int c = 0; c < N; ++c) v[u][c] = ld<NT>(psi + (b ^ off_lo<D>(a.off, c)));
+        }
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                V acc;
+                acc.x = 0;
+                acc.y = 0;
+#pragma unroll
+                for (int c = 0; c < N; ++c) cmac(acc, m[u][2 * (r * N + c)], m[u][2 * (r * N + c) + 1], v[u][c]);
+                st<NT>(psi + (base[u] ^ off_lo<D>(a.off, r)), acc);
+            }
+        }
+    }
+    // tail: items not covered by full iterations, one per thread
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = nfull * per_iter + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += stride) {
+        const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(i >> a.log_ngroups));
         const uint64_t g = i & (a.ngroups - 1);
         const uint32_t bid = a.blk[bs];
-        uint64_t base = deposit(g, a.lowmask, a.k);
+        uint64_t b = deposit(g, a.lowmask, a.k);
         for (int j = 0; j < a.k - D; ++j)
-            if ((bid >> j) & 1u) base ^= a.off[D + j];
-        const R *m = mat + (size_t)bs * (2 * N * N);
-        V v[N];
+            if ((bid >> j) & 1u) b ^= a.off[D + j];
+        const R *mm = mat + (size_t)bs * (2 * N * N);
+        V w[N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) v[c] = psi[base ^ off_lo<D>(a.off, c)];
+        for (int c = 0; c < N; ++c) w[c] = psi[b ^ off_lo<D>(a.off, c)];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             V acc;
             acc.x = 0;
             acc.y = 0;
 #pragma unroll
-            for (int c = 0; c < N; ++c) cmac(acc, m[2 * (r * N + c)], m[2 * (r * N + c) + 1], v[c]);
-            psi[base ^ off_lo<D>(a.off, r)] = acc;
+            for (int c = 0; c < N; ++c) cmac(acc, mm[2 * (r * N + c)], mm[2 * (r * N + c) + 1], w[c]);
+            psi[b ^ off_lo<D>(a.off, r)] = acc;
         }
     }
 }
 
 // ------------------------------------------------------------------ tile
+// LDS layout: 16-byte chunk c of the tile is stored at chunk swz(c), which
+// XORs the chunk's column (c mod 16) with a hash of its row (c / 16).  Rows
+// stay in place, so the coalesced tile load/store phases remain conflict-free,
+// while group reads at power-of-two strides (consecutive groups skip the low
+// target bits) spread over all banks.
+__device__ __forceinline__ uint32_t swz(uint32_t c) { return c ^ (((c >> 4) ^ (c >> 8)) & 15u); }
+
+template <int S>  // S = log2(amplitudes per 16-byte chunk)
+__device__ __forceinline__ uint32_t lds_elem(uint32_t p) {
+    return (swz(p >> S) << S) | (p & ((1u << S) - 1));
+}
+
+// Global 16-byte chunk index of tile chunk c.
+__device__ __forceinline__ uint64_t tile_chunk_addr(uint32_t c, uint64_t tbase, uint32_t rcl, int apc_log,
+                                                    const PassArgs &a) {
+    const uint32_t r = c >> rcl;
+    uint64_t x = tbase;
+    for (int j = 0; j < a.khi; ++j)
+        if ((r >> j) & 1u) x |= 1ull << a.qhi[j];
+    return (x >> apc_log) + (c & ((1u << rcl) - 1));
+}
+
 // Tile position of global index bits: window bits [0, W) keep their place,
 // high target j lands on bit W + j.  TWOBUF: the group's inputs are re-read
 // from LDS for each output row and the results go to a second LDS tile (used
@@ -102,50 +190,41 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
                                               PassArgs a) {
     using V = typename Amp<R>::T;
     constexpr int N = 1 << D;
+    constexpr int S = sizeof(V) == 16 ? 0 : 1;   // log2(amplitudes per 16-byte chunk)
     extern __shared__ uint4 lds_raw[];
     V *tile = reinterpret_cast<V *>(lds_raw);
-    V *tout = TWOBUF ? tile + ((size_t)1 << a.tb) : tile;
+    const uint32_t tile_amps = 1u << a.tb;
+    V *tout = TWOBUF ? tile + tile_amps : tile;
     uint4 *tile16 = lds_raw;
     uint4 *tout16 = reinterpret_cast<uint4 *>(tout);
     const uint4 *src16 = reinterpret_cast<const uint4 *>(psi_r);
     uint4 *dst16 = reinterpret_cast<uint4 *>(psi_r);
-    V *psi = reinterpret_cast<V *>(psi_r);
-    (void)psi;
 
-    constexpr uint32_t APC = 16 / sizeof(V);           // amplitudes per 16-byte chunk
-    const uint32_t chunks = (1u << a.tb) / APC;        // 16-byte chunks per tile
-    const uint32_t run_chunks_log = a.W - (APC == 2 ? 1 : 0);
-    const uint32_t items = (1u << (a.tb - a.k)) * a.nblk;
+    const uint32_t chunks = tile_amps >> S;
+    const uint32_t rcl = a.W - S;                     // log2(chunks per contiguous run)
     const uint32_t log_gt = a.tb - a.k;
+    const uint32_t items = (1u << log_gt) * a.nblk;
+    const bool batched = chunks >= 8 * 256;           // chunks is a power of two
 
     for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         // global index of the tile's first amplitude: t above the window,
         // with zeros inserted at the high targets
         const uint64_t tbase = deposit(t << a.W, a.hilowmask, a.khi);
         // ---- load 2^kH runs of 2^W amplitudes, 16 bytes per lane
-        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * blockDim.x) {
-            uint4 buf[8];
+        if (batched) {
+            for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
+                uint4 buf[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * blockDim.x;
-                if (c < chunks) {
-                    const uint32_t r = c >> run_chunks_log;
-                    const uint32_t w = c & ((1u << run_chunks_log) - 1);
-                    uint64_t x = tbase;
-                    for (int j = 0; j < a.khi; ++j)
-                        if ((r >> j) & 1u) x |= 1ull << a.qhi[j];
-                    buf[u] = src16[(x / APC) + w];
-                }
-            }
+                for (int u = 0; u < 8; ++u) buf[u] = src16[tile_chunk_addr(c0 + u * 256, tbase, rcl, S, a)];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * blockDim.x;
-                if (c < chunks) tile16[c] = buf[u];
+                for (int u = 0; u < 8; ++u) tile16[swz(c0 + u * 256)] = buf[u];
             }
+        } else {
+            for (uint32_t c = threadIdx.x; c < chunks; c += 256) tile16[swz(c)] = src16[tile_chunk_addr(c, tbase, rcl, S, a)];
         }
         __syncthreads();
         // ---- update the tile's (group, block) items
-        for (uint32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        for (uint32_t it = threadIdx.x; it < items; it += 256) {
             uint32_t bs = it >> log_gt;
             if (UNI) bs = __builtin_amdgcn_readfirstlane(bs);
             const uint32_t gl = it & ((1u << log_gt) - 1);
@@ -170,7 +249,7 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
             if (!TWOBUF) {
                 V v[N];
 #pragma unroll
-                for (int c = 0; c < N; ++c) v[c] = tile[pos ^ olo[c]];
+                for (int c = 0; c < N; ++c) v[c] = tile[lds_elem<S>(pos ^ olo[c])];
 #pragma unroll
                 for (int r = 0; r < N; ++r) {
                     V acc;
@@ -178,7 +257,7 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
                     acc.y = 0;
 #pragma unroll
                     for (int c = 0; c < N; ++c) cmac(acc, m[2 * (r * N + c)], m[2 * (r * N + c) + 1], v[c]);
-                    tile[pos ^ olo[r]] = acc;
+                    tile[lds_elem<S>(pos ^ olo[r])] = acc;
                 }
             } else {
                 constexpr int RC = 8;
@@ -189,7 +268,7 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
                     for (int r = 0; r < RC; ++r) acc[r].x = acc[r].y = 0;
 #pragma unroll
                     for (int c = 0; c < N; ++c) {
-                        const V vc = tile[pos ^ olo[c]];
+                        const V vc = tile[lds_elem<S>(pos ^ olo[c])];
 #pragma unroll
                         for (int r = 0; r < RC; ++r)
                             cmac(acc[r], m[2 * ((r0 + r) * N + c)], m[2 * ((r0 + r) * N + c) + 1], vc);
@@ -201,7 +280,7 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
 #pragma unroll
                         for (int j = 0; j < D; ++j)
                             if ((rr >> j) & 1) o ^= a.toff[j];
-                        tout[pos ^ o] = acc[r];
+                        tout[lds_elem<S>(pos ^ o)] = acc[r];
                     }
                 }
             }
@@ -209,45 +288,67 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
         __syncthreads();
         // ---- store.  Identity blocks were never touched, so their tile copy is
         // the input.  (TWOBUF is used only for k = d = 6: one block, always active.)
-        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * blockDim.x) {
-            uint4 buf[8];
+        if (batched) {
+            for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
+                uint4 buf[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * blockDim.x;
-                if (c < chunks) buf[u] = tout16[c];
-            }
+                for (int u = 0; u < 8; ++u) buf[u] = tout16[swz(c0 + u * 256)];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * blockDim.x;
-                if (c < chunks) {
-                    const uint32_t r = c >> run_chunks_log;
-                    const uint32_t w = c & ((1u << run_chunks_log) - 1);
-                    uint64_t x = tbase;
-                    for (int j = 0; j < a.khi; ++j)
-                        if ((r >> j) & 1u) x |= 1ull << a.qhi[j];
-                    dst16[(x / APC) + w] = buf[u];
-                }
+                for (int u = 0; u < 8; ++u) dst16[tile_chunk_addr(c0 + u * 256, tbase, rcl, S, a)] = buf[u];
             }
+        } else {
+            for (uint32_t c = threadIdx.x; c < chunks; c += 256) dst16[tile_chunk_addr(c, tbase, rcl, S, a)] = tout16[swz(c)];
         }
         __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ dispatch
-template <typename R>
-static hipError_t launch_direct(int D, bool uni, R *psi, const R *m, const PassArgs &a, int grid,
-                                int wg, hipStream_t s) {
-#define CAST_DIRECT(DD)                                                                         \
-    case DD:                                                                                    \
-        if (uni) hipLaunchKernelGGL((k_direct<DD, R, true>), dim3(grid), dim3(wg), 0, s, psi, m, a); \
-        else hipLaunchKernelGGL((k_direct<DD, R, false>), dim3(grid), dim3(wg), 0, s, psi, m, a);     \
-        break;
+template <int DD, typename R, int IPT, bool NT>
+static void launch_one(R *psi, const R *m, const PassArgs &a, int grid, hipStream_t s) {
+    // several items per thread only pay (and only fit) for small blocks
+    if constexpr (IPT == 1 || DD <= 3)
+        hipLaunchKernelGGL((k_direct<DD, R, IPT, NT>), dim3(grid), dim3(256), 0, s, psi, m, a);
+}
+
+template <typename R, int IPT, bool NT>
+static void launch_direct_t(int D, R *psi, const R *m, const PassArgs &a, int grid, hipStream_t s) {
+#define CAST_DIRECT(DD) \
+    case DD: launch_one<DD, R, IPT, NT>(psi, m, a, grid, s); break;
     switch (D) {
-        CAST_DIRECT(0) CAST_DIRECT(1) CAST_DIRECT(2) CAST_DIRECT(3) CAST_DIRECT(4) CAST_DIRECT(5)
-        CAST_DIRECT(6)
-        default: return hipErrorInvalidValue;
+        CAST_DIRECT(0) CAST_DIRECT(1) CAST_DIRECT(2) CAST_DIRECT(3) CAST_DIRECT(4) CAST_DIRECT(5) CAST_DIRECT(6)
+        default: break;
     }
 #undef CAST_DIRECT
+}
+
+// Items per thread: enough loads in flight for small blocks, one item when a
+// block already needs many registers.
+static int direct_ipt(int D, cast_dtype dt) {
+    const int amps_cap = dt == CAST_C128 ? 8 : 16;   // amplitudes a lane holds across its items
+    int ipt = tuning().direct_ipt;
+    while (ipt > 1 && (ipt * (1 << D) > amps_cap || D > 3)) ipt >>= 1;
+    return ipt;
+}
+
+template <typename R>
+static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const PassArgs &a, hipStream_t s) {
+    const int ipt = direct_ipt(D, dt);
+    const bool nt = tuning().direct_nt != 0;
+    const uint64_t items = a.ngroups * a.nblk;
+    uint64_t grid = (items + 256ull * ipt - 1) / (256ull * ipt);
+    if (grid > (uint64_t)tuning().max_grid) grid = tuning().max_grid;
+    if (grid < 1) grid = 1;
+    const int g = (int)grid;
+    switch (ipt * 2 + (nt ? 1 : 0)) {
+        case 2: launch_direct_t<R, 1, false>(D, psi, m, a, g, s); break;
+        case 3: launch_direct_t<R, 1, true>(D, psi, m, a, g, s); break;
+        case 4: launch_direct_t<R, 2, false>(D, psi, m, a, g, s); break;
+        case 5: launch_direct_t<R, 2, true>(D, psi, m, a, g, s); break;
+        case 8: launch_direct_t<R, 4, false>(D, psi, m, a, g, s); break;
+        case 9: launch_direct_t<R, 4, true>(D, psi, m, a, g, s); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -287,7 +388,14 @@ static hipError_t launch_tile(int D, bool uni, bool twobuf, R *psi, const R *m, 
 
 // Registers hold 2^d input amplitudes per lane; beyond this the kernel
 // re-reads inputs from LDS (TWOBUF).
-static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 6; }
+static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 5; }
+
+int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p) {
+    const Tuning &tu = tuning();
+    if (p.d > max_reg_d(dt)) return 2;
+    if (p.q[0] >= tu.direct_min_q[dt] && (n - p.k) >= 6) return 0;
+    return 1;
+}
 
 cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
                         hipStream_t stream) {
@@ -306,22 +414,19 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             if ((p.L[i] >> s) & 1u) o |= 1ull << p.q[s];
         a.off[i] = o;
     }
-    const bool twobuf = D > max_reg_d(dt);
-    const bool direct = !twobuf && p.q[0] >= tu.direct_min_q[dt] && (n - k) >= 6;
+    const int kind = pass_kernel_kind(n, dt, p);
+    const bool twobuf = kind == 2;
+    const bool direct = kind == 0;
     hipError_t e;
     if (direct) {
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
         a.log_ngroups = n - k;
         a.ngroups = 1ull << (n - k);
-        const uint64_t items = a.ngroups * a.nblk;
-        const int wg = tu.wg_direct;
-        uint64_t grid = (items + wg - 1) / wg;
-        if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
-        const bool uni = true;  // ngroups >= 64 and a multiple of 64
+        // ngroups >= 64 (n - k >= 6), so every 64-lane slice of items shares a block
         if (dt == CAST_C128)
-            e = launch_direct<double>(D, uni, (double *)psi, (const double *)dmat, a, (int)grid, wg, stream);
+            e = launch_direct<double>(D, dt, (double *)psi, (const double *)dmat, a, stream);
         else
-            e = launch_direct<float>(D, uni, (float *)psi, (const float *)dmat, a, (int)grid, wg, stream);
+            e = launch_direct<float>(D, dt, (float *)psi, (const float *)dmat, a, stream);
     } else {
         int tb = tu.tile_bits[dt];
         if (twobuf) tb = 12;
@@ -350,7 +455,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             a.toff[i] = o;
         }
         a.ntiles = 1ull << (n - tb);
-        const int wg = tu.wg_tile;
+        const int wg = 256;
         uint64_t grid = a.ntiles;
         if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
         const bool uni = (tb - k) >= 6;

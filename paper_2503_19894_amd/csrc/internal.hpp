@@ -65,13 +65,16 @@ struct DeviceMatrix {                // a plan's block matrices in the state dty
 };
 
 struct Tuning {                      // launch parameters chosen per (dtype, kernel)
-    int direct_min_q[3] = {0, 5, 4}; // smallest target for the direct kernel, by dtype
-    int tile_bits[3] = {0, 13, 12};  // LDS tile size log2(amplitudes), by dtype
-    int wg_direct = 256;
-    int wg_tile = 256;
+    int direct_min_q[3] = {0, 4, 4}; // smallest target for the direct kernel, by dtype
+    int tile_bits[3] = {0, 12, 12};  // LDS tile size log2(amplitudes), by dtype
+    int direct_ipt = 4;              // work items per thread per iteration (capped by registers)
+    int direct_nt = 1;               // non-temporal loads/stores in the direct kernel
     int max_grid = 1 << 16;
 };
 Tuning &tuning();
+
+// Kernel a pass uses: 0 direct, 1 LDS tile, 2 LDS tile with two buffers.
+int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p);
 
 // Queues one pass on `stream`.  `dmat` holds the plan's blocks in dtype `dt`.
 cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
