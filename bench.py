@@ -27,14 +27,15 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 
-KERNEL_NAMES = {0: "k_direct", 1: "k_tile", 2: "k_tile"}
 
 
 def kernel_label(info, dtype_name):
     kind = info["kernel"]
     r = "double" if dtype_name == "c128" else "float"
+    if kind == 3:
+        return f"k_diag<{r}, 4>"
     if kind == 0:
-        return f"k_direct<{info['d']}, {r}, true>"
+        return f"k_direct<{info['d']}, {r}>"
     uni = "true"  # tiles hold >= 64 groups at n = 30
     two = "true" if kind == 2 else "false"
     return f"k_tile<{info['d']}, {r}, {uni}, {two}>"

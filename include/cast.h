@@ -166,7 +166,8 @@ cast_status apply_circuit(cast_sv *sv, const cast_fused *f);
 cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *f, float *pass_ms);
 
 /* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct
- * gather), 1 (LDS tile) or 2 (LDS tile, two buffers), *d the block dimension,
+ * gather), 1 (LDS tile), 2 (LDS tile, two buffers), 3 (elementwise diagonal)
+ * or -1 (identity, skipped), *d the block dimension,
  * and the pass's algorithmic HBM bytes (every amplitude of a non-identity
  * block read once and written once) and flops (8 per complex multiply-add
  * over the non-identity blocks). */

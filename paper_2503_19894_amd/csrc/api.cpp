@@ -36,6 +36,7 @@ Tuning &tuning() {
         env("CAST_MAX_GRID", x.max_grid);
         env("CAST_DIRECT_IPT", x.direct_ipt);
         env("CAST_DIRECT_NT", x.direct_nt);
+        env("CAST_USE_DIAG", x.use_diag);
         return x;
     }();
     return t;
@@ -100,10 +101,7 @@ void dev_free(void *ptr) {
 // ----------------------------------------------------------------- uploads
 template <typename R>
 static void pack(const PassPlan &p, std::vector<R> &dst) {
-    for (const cplx &z : p.mat) {
-        dst.push_back((R)z.real());
-        dst.push_back((R)z.imag());
-    }
+    pack_plan<R>(p, dst);
 }
 
 cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,

@@ -64,6 +64,7 @@ __device__ __forceinline__ void cmac(V &acc, R mre, R mim, const V &v) {
 // store.  NT: non-temporal hint on the state's loads and stores (the state is
 // streamed once per pass).
 typedef double native_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int native_u4 __attribute__((ext_vector_type(4)));
 typedef float native_f2 __attribute__((ext_vector_type(2)));
 template <typename V> struct Native;
 template <> struct Native<double2> { using T = native_d2; };
@@ -116,7 +117,8 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
             for (int j = 0; j < a.k - D; ++j)
                 if ((bid >> j) & 1u) b ^= a.off[D + j];
             base[u] = b;
-            m[u] = mat + (size_t)bs * (2 * N * N);
+            // diagonal plans keep the full diagonal, indexed by block id
+            m[u] = mat + (size_t)(D == 0 ? bid : bs) * (2 * N * N);
 #pragma unroll
             for (int c = 0; c < N; ++c) v[u][c] = ld<NT>(psi + (b ^ off_lo<D>(a.off, c)));
         }
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
         uint64_t b = deposit(g, a.lowmask, a.k);
         for (int j = 0; j < a.k - D; ++j)
             if ((bid >> j) & 1u) b ^= a.off[D + j];
-        const R *mm = mat + (size_t)bs * (2 * N * N);
+        const R *mm = mat + (size_t)(D == 0 ? bid : bs) * (2 * N * N);
         V w[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) w[c] = psi[b ^ off_lo<D>(a.off, c)];
@@ -155,6 +157,80 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
             for (int c = 0; c < N; ++c) cmac(acc, mm[2 * (r * N + c)], mm[2 * (r * N + c) + 1], w[c]);
             psi[b ^ off_lo<D>(a.off, r)] = acc;
         }
+    }
+}
+
+// ------------------------------------------------------------------ diagonal
+// A diagonal gate (d = 0) multiplies amplitude x by D[j(x)], j(x) = the bits
+// of x at the targets.  Lanes stream consecutive 16-byte chunks of the state
+// whatever the targets are, so every access is coalesced; a lane whose
+// amplitudes all have D[j] = 1 issues neither the load nor the store, and
+// whole cache lines of such amplitudes never leave HBM.
+template <typename R, int U>
+__global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__restrict__ table, DiagArgs a) {
+    using V = typename Amp<R>::T;
+    constexpr int S = sizeof(V) == 16 ? 0 : 1;   // log2(amplitudes per 16-byte chunk)
+    __shared__ V tab[64];
+    const int D = 1 << a.k;
+    for (int j = threadIdx.x; j < D; j += 256) {
+        V t;
+        t.x = table[2 * j];
+        t.y = table[2 * j + 1];
+        tab[j] = t;
+    }
+    __syncthreads();
+    native_u4 *p16 = reinterpret_cast<native_u4 *>(psi_r);
+    auto jof = [&](uint64_t x) {
+        uint32_t j = 0;
+        for (int i = 0; i < a.k; ++i) j |= (uint32_t)((x >> a.q[i]) & 1u) << i;
+        return j;
+    };
+    auto update = [&](native_u4 &w, uint64_t c) {
+        V *v = reinterpret_cast<V *>(&w);
+#pragma unroll
+        for (int h = 0; h < (1 << S); ++h) {
+            const uint32_t j = jof((c << S) | (uint64_t)h);
+            if ((a.amask >> j) & 1u) {
+                const V t = tab[j];
+                const R re = v[h].x * t.x - v[h].y * t.y;
+                const R im = v[h].x * t.y + v[h].y * t.x;
+                v[h].x = re;
+                v[h].y = im;
+            }
+        }
+    };
+    auto active = [&](uint64_t c) {
+        bool any = false;
+#pragma unroll
+        for (int h = 0; h < (1 << S); ++h) any |= (a.amask >> jof((c << S) | (uint64_t)h)) & 1u;
+        return any;
+    };
+    constexpr uint64_t per = 256ull * U;
+    const uint64_t nfull = a.nchunks / per;
+    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
+        native_u4 w[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
+            act[u] = active(c);
+            if (act[u]) w[u] = __builtin_nontemporal_load(p16 + c);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
+            if (act[u]) {
+                update(w[u], c);
+                __builtin_nontemporal_store(w[u], p16 + c);
+            }
+        }
+    }
+    for (uint64_t c = nfull * per + (uint64_t)blockIdx.x * 256 + threadIdx.x; c < a.nchunks;
+         c += (uint64_t)gridDim.x * 256) {
+        if (!active(c)) continue;
+        native_u4 w = p16[c];
+        update(w, c);
+        p16[c] = w;
     }
 }
 
@@ -245,7 +321,7 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
                     if ((c >> j) & 1) o ^= a.toff[j];
                 olo[c] = o;
             }
-            const R *m = mat + (size_t)bs * (2 * N * N);
+            const R *m = mat + (size_t)(D == 0 ? bid : bs) * (2 * N * N);
             if (!TWOBUF) {
                 V v[N];
 #pragma unroll
@@ -392,6 +468,7 @@ static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 5; }
 
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p) {
     const Tuning &tu = tuning();
+    if (p.d == 0 && tu.use_diag) return 3;
     if (p.d > max_reg_d(dt)) return 2;
     if (p.q[0] >= tu.direct_min_q[dt] && (n - p.k) >= 6) return 0;
     return 1;
@@ -418,7 +495,25 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
     const bool twobuf = kind == 2;
     const bool direct = kind == 0;
     hipError_t e;
-    if (direct) {
+    if (kind == 3) {
+        DiagArgs g;
+        memset(&g, 0, sizeof g);
+        g.k = k;
+        for (int i = 0; i < k; ++i) g.q[i] = p.q[i];
+        for (uint32_t b : p.blk) g.amask |= 1ull << b;
+        g.nchunks = ((uint64_t)1 << n) * amp_bytes(dt) / 16;
+        if (g.nchunks == 0) g.nchunks = 1;   // c64, n = 1: one chunk holds both amplitudes
+        constexpr int U = 4;
+        uint64_t grid = (g.nchunks + 256 * U - 1) / (256 * U);
+        if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
+        if (dt == CAST_C128)
+            hipLaunchKernelGGL((k_diag<double, U>), dim3((int)grid), dim3(256), 0, stream, (double *)psi,
+                               (const double *)dmat, g);
+        else
+            hipLaunchKernelGGL((k_diag<float, U>), dim3((int)grid), dim3(256), 0, stream, (float *)psi,
+                               (const float *)dmat, g);
+        e = hipGetLastError();
+    } else if (direct) {
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
         a.log_ngroups = n - k;
         a.ngroups = 1ull << (n - k);

@@ -69,11 +69,30 @@ struct Tuning {                      // launch parameters chosen per (dtype, ker
     int tile_bits[3] = {0, 12, 12};  // LDS tile size log2(amplitudes), by dtype
     int direct_ipt = 4;              // work items per thread per iteration (capped by registers)
     int direct_nt = 1;               // non-temporal loads/stores in the direct kernel
-    int max_grid = 1 << 16;
+    int use_diag = 1;                // elementwise kernel for diagonal passes
+    int max_grid = 1 << 20;
 };
 Tuning &tuning();
 
-// Kernel a pass uses: 0 direct, 1 LDS tile, 2 LDS tile with two buffers.
+// Kernel a pass uses: 0 direct, 1 LDS tile, 2 LDS tile with two buffers,
+// 3 elementwise diagonal.
+// Device layout of a plan's matrices (reals of the state dtype): the active
+// blocks, or for diagonal plans (d = 0) the full diagonal of 2^k entries.
+template <typename R>
+void pack_plan(const PassPlan &p, std::vector<R> &dst) {
+    if (p.d == 0) {
+        const size_t D = (size_t)1 << p.k;
+        for (size_t j = 0; j < D; ++j) {
+            dst.push_back((R)p.full[j * D + j].real());
+            dst.push_back((R)p.full[j * D + j].imag());
+        }
+        return;
+    }
+    for (const cplx &z : p.mat) {
+        dst.push_back((R)z.real());
+        dst.push_back((R)z.imag());
+    }
+}
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p);
 
 // Queues one pass on `stream`.  `dmat` holds the plan's blocks in dtype `dt`.

@@ -22,4 +22,12 @@ struct PassArgs {
     int qhi[6];             // tile: high targets, ascending
 };
 
+// Kernel argument block of a diagonal pass (every block 1 x 1).
+struct DiagArgs {
+    uint64_t amask;         // bit j set: local index j has a phase != 1
+    uint64_t nchunks;       // 16-byte chunks in the state
+    int k;
+    int q[6];               // sorted targets
+};
+
 }  // namespace cast
