@@ -127,6 +127,85 @@ def cpu_baseline(n, target_s=15.0, max_gates=8):
             "sample": f"first {done} unfused QFT-{n} gates on a 2^{n} FP64 state, {t_total:.1f} s"}
 
 
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "k_diag_qft30_c128_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19894_amd", "csrc",
+                             "apply.hip")
+
+
+def source_digest():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is missing or the kernel source changed since."""
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    meta = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
+    if meta.get("kernel_source_sha256_16") != source_digest():
+        return None
+    for l in lines:
+        if l.startswith(kernel + " |"):
+            return float(l.split("|")[4])
+    return None
+
+
+def summarize_kernel_trace(stats_csv, command):
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"# rocprofv3 kernel-trace summary", f"# command: {command}",
+           f"# kernel_source_sha256_16: {source_digest()}",
+           f"{'kernel':78s} {'calls':>6s} {'avg_ms':>9s} {'total_ms':>10s} {'min_ms':>8s} {'max_ms':>8s} {'pct':>6s}"]
+    for r in rows[:14]:
+        out.append(f"{r['Name'][:78]:78s} {int(r['Calls']):6d} {float(r['AverageNs'])/1e6:9.4f} "
+                   f"{float(r['TotalDurationNs'])/1e6:10.1f} {float(r['MinNs'])/1e6:8.3f} {float(r['MaxNs'])/1e6:8.3f} "
+                   f"{float(r['Percentage']):6.2f}")
+    return "\n".join(out)
+
+
+def summarize_traffic(fetch_csv, write_csv, command_fetch, command_write):
+    """Per-kernel HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for the 1 GiB device copy
+    that --calibrate-copy runs first."""
+    import csv
+    import collections
+
+    def load(path, counter):
+        per = collections.defaultdict(list)
+        first_copy = None
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            if first_copy is None and "copyBuffer" in r["Kernel_Name"]:
+                first_copy = float(r["Counter_Value"])
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return per, first_copy
+
+    f, fcopy = load(fetch_csv, "FETCH_SIZE")
+    w, wcopy = load(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    ff, wf = gib_kib / fcopy, gib_kib / wcopy
+    out = ["# HBM traffic per launch from rocprofv3 PMC counters (two runs)",
+           f"# command_fetch: {command_fetch}", f"# command_write: {command_write}",
+           f"# kernel_source_sha256_16: {source_digest()}",
+           f"# calibration: 1 GiB device copy reads FETCH_SIZE {fcopy:.1f} KiB (factor {ff:.4f}), "
+           f"WRITE_SIZE {wcopy:.1f} KiB (factor {wf:.4f})",
+           "# columns: kernel | launches | fetch_KiB_avg | write_KiB_avg | scaled_bytes_per_launch"]
+    names = sorted(set(f) | set(w), key=lambda k: -sum(f.get(k, [0])) / max(1, len(f.get(k, [1]))))
+    for name in names:
+        fv, wv = f.get(name, []), w.get(name, [])
+        if not fv or not wv:
+            continue
+        fa, wa = sum(fv) / len(fv), sum(wv) / len(wv)
+        label = name.split("(")[0].replace("void cast::", "")
+        out.append(f"{label} | {len(fv)} | {fa:.1f} | {wa:.1f} | {(fa * ff + wa * wf) * 1024:.0f}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,7 +215,17 @@ def main():
     ap.add_argument("--k-max", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
+    ap.add_argument("--summarize-kernel-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
     args = ap.parse_args()
+    if args.summarize_kernel_trace:
+        print(summarize_kernel_trace(*args.summarize_kernel_trace))
+        return
+    if args.summarize_traffic:
+        print(summarize_traffic(*args.summarize_traffic))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the state-vector path here is built and measured on a single "
               "MI355X; runs on more than one GPU are not supported.", file=sys.stderr)
@@ -146,14 +235,22 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     main_run = run_gpu(args.n, args.k_max, "c128", args.steps, args.warmup)
     extras = {}
     if not args.no_c64:
         extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup)
     dom = main_run["kernels"][main_run["dominant"]]
+    traffic = recorded_traffic(main_run["dominant"])
     roof = {"bound": "hbm", "kernel": main_run["dominant"], "achieved": round(dom["achieved_gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
+            "traffic": traffic, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
     line = {
