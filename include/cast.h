@@ -204,6 +204,57 @@ cast_status adjoint_grad(const cast_sv *init, const cast_gate *gates, size_t n_g
                          const cast_pauli_term *terms, size_t n_terms,
                          double *energy, double *grad);
 
+/* ------------------------------------------------------ batched gradients */
+
+/* Many parametrised circuits evaluated together on one GPU: the same
+ * structure with different parameter sets (variational algorithms run the
+ * same circuit thousands of times), or circuits of different qubit counts.
+ * Each instance i has n_qubits[i] qubits (2..34), its own gate list
+ * (1- and 2-qubit gates; parametrised gates as in cast_gate), n_params[i]
+ * parameters and Pauli sum H_i, and starts from init_kind[i]:
+ * CAST_INIT_ZERO |0...0>, CAST_INIT_PLUS |+...+>, or CAST_INIT_STATE a copy
+ * of init_states[i] (a state of the same n and dtype that must stay alive
+ * while the batch is used).  init_kind may be NULL (all |0...0>).
+ *
+ * Every instance runs: forward gates, lambda = H psi, energy <psi|lambda>,
+ * and the reverse adjoint sweep; op s of every instance forms global step s.
+ * mode CAST_BATCH_STEPS queues one launch per global step;
+ * CAST_BATCH_STEPS_GRAPH captures those launches once in a hipGraph and
+ * replays it; CAST_BATCH_PERSISTENT_GRAPH captures one persistent launch in
+ * which workgroups take (step, instance, slice) items in order from a device
+ * counter, each waiting (bounded) until its instance has finished the
+ * previous op.  Results are identical in all modes (fixed reduction order).
+ * The batch owns device states (psi and lambda per instance), a pinned
+ * matrix buffer and its own stream; the caller owns *out (batch_destroy). */
+enum { CAST_INIT_ZERO = 0, CAST_INIT_PLUS = 1, CAST_INIT_STATE = 2 };
+enum { CAST_BATCH_STEPS = 0, CAST_BATCH_STEPS_GRAPH = 1, CAST_BATCH_PERSISTENT_GRAPH = 2 };
+
+typedef struct cast_batch cast_batch;
+
+cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const cast_gate *const *circuits,
+                         const size_t *n_gates, const size_t *n_params, const cast_pauli_term *const *hamiltonians,
+                         const size_t *n_terms, const int *init_kind, const cast_sv *const *init_states, int mode,
+                         cast_batch **out);
+
+/* Binds theta[i] (n_params[i] doubles per instance; may be NULL for
+ * instances without parameters), runs the whole batch and writes energies[i]
+ * and grads[i][p] = dE_i/dtheta_i[p] (FP64).  Synchronous.  CAST_EHIP if a
+ * persistent-mode dependency wait exceeded its bound (results invalid). */
+cast_status batch_run(cast_batch *b, const double *const *theta, double *energies, double *const *grads);
+
+/* Global steps, total work items of the persistent launch, and bytes of the
+ * batch's device states (psi and lambda of every instance). */
+cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items, double *state_bytes);
+
+void batch_destroy(cast_batch *b);
+
+/* batch_create + batch_run + batch_destroy in one call. */
+cast_status adjoint_grad_batch(int n_inst, const int *n_qubits, cast_dtype dt, const cast_gate *const *circuits,
+                               const size_t *n_gates, const double *const *theta, const size_t *n_params,
+                               const cast_pauli_term *const *hamiltonians, const size_t *n_terms,
+                               const int *init_kind, const cast_sv *const *init_states, int mode,
+                               double *energies, double *const *grads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,7 +75,25 @@ SIGNATURES = {
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
                                     ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
                                     _c_double_p, _c_double_p]),
+    "batch_create": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.c_int, ctypes.POINTER(ctypes.POINTER(cast_gate)),
+                                    ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.POINTER(cast_pauli_term)), ctypes.POINTER(ctypes.c_size_t),
+                                    _c_int_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_c_double_p), _c_double_p,
+                                 ctypes.POINTER(_c_double_p)]),
+    "batch_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_uint64), _c_double_p]),
+    "batch_destroy": (None, [ctypes.c_void_p]),
+    "adjoint_grad_batch": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.POINTER(cast_gate)), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(_c_double_p), ctypes.POINTER(ctypes.c_size_t),
+                                          ctypes.POINTER(ctypes.POINTER(cast_pauli_term)),
+                                          ctypes.POINTER(ctypes.c_size_t), _c_int_p, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.c_int, _c_double_p, ctypes.POINTER(_c_double_p)]),
 }
+
+INIT_ZERO, INIT_PLUS, INIT_STATE = 0, 1, 2
+BATCH_STEPS, BATCH_STEPS_GRAPH, BATCH_PERSISTENT_GRAPH = 0, 1, 2
 
 for _name, (_res, _args) in SIGNATURES.items():
     _f = getattr(_lib, _name)
@@ -296,6 +314,63 @@ def adjoint(init: StateVector, gates, theta, terms):
     return e.value, grad[:th.size].copy()
 
 
+class Batch:
+    """Batched energies and adjoint gradients of many parametrised circuits
+    (one library batch: device states, pinned matrices, optional hipGraph).
+
+    circuits[i]: gate records of instance i (1- and 2-qubit gates),
+    n_qubits[i], n_params[i], hamiltonians[i]: Pauli-term records; init[i]:
+    "zero", "plus" or a StateVector of the same size and dtype."""
+
+    def __init__(self, circuits, n_qubits, n_params, hamiltonians, dtype=torch.complex128, init=None,
+                 mode=BATCH_STEPS_GRAPH):
+        B = len(circuits)
+        self.B = B
+        self.n_params = [int(p) for p in n_params]
+        self._gates = [GateArray(c) for c in circuits]
+        self._terms = [pauli_terms(h) for h in hamiltonians]
+        self._init = init
+        nq = (ctypes.c_int * B)(*[int(n) for n in n_qubits])
+        circ = (ctypes.POINTER(cast_gate) * B)(*[ctypes.cast(g.arr, ctypes.POINTER(cast_gate)) for g in self._gates])
+        ng = (ctypes.c_size_t * B)(*[g.n for g in self._gates])
+        npar = (ctypes.c_size_t * B)(*self.n_params)
+        hp = (ctypes.POINTER(cast_pauli_term) * B)(
+            *[ctypes.cast(t, ctypes.POINTER(cast_pauli_term)) for t in self._terms])
+        nt = (ctypes.c_size_t * B)(*[len(h) for h in hamiltonians])
+        kinds = (ctypes.c_int * B)()
+        srcs = (ctypes.c_void_p * B)()
+        for i in range(B):
+            it = "zero" if init is None else init[i]
+            if isinstance(it, StateVector):
+                kinds[i], srcs[i] = INIT_STATE, it.handle.value
+            else:
+                kinds[i] = {"zero": INIT_ZERO, "plus": INIT_PLUS}[it]
+        dt = C128 if dtype == torch.complex128 else C64
+        h = ctypes.c_void_p()
+        batch_create(B, nq, dt, circ, ng, npar, hp, nt, kinds, srcs, int(mode), ctypes.byref(h))
+        self.handle = h
+
+    def info(self):
+        ns, items, sb = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_double()
+        batch_info(self.handle, ctypes.byref(ns), ctypes.byref(items), ctypes.byref(sb))
+        return {"steps": ns.value, "items": items.value, "state_bytes": sb.value}
+
+    def run(self, thetas):
+        """thetas[i]: n_params[i] angles.  Returns (energies [B], grads list)."""
+        th = [np.ascontiguousarray(t, dtype=np.float64).reshape(-1) for t in thetas]
+        gr = [np.zeros(max(1, p)) for p in self.n_params]
+        tp = (_c_double_p * self.B)(*[_dptr(t) for t in th])
+        gp = (_c_double_p * self.B)(*[_dptr(g) for g in gr])
+        e = np.zeros(self.B)
+        batch_run(self.handle, tp, _dptr(e), gp)
+        return e, [g[:p].copy() for g, p in zip(gr, self.n_params)]
+
+    def __del__(self, _destroy=_lib.batch_destroy):
+        if getattr(self, "handle", None):
+            _destroy(self.handle)
+            self.handle = None
+
+
 class CircuitEnergy(torch.autograd.Function):
     """E[b] = <psi(theta_b)|H|psi(theta_b)> for theta of shape [B, P] (or [P]);
     backward returns grad_out[b] * dE[b]/dtheta_b from the adjoint sweep done
@@ -304,15 +379,22 @@ class CircuitEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, n, gates, terms, dtype=torch.complex128):
         th = theta.detach().to("cpu", torch.float64)
-        flat = th.reshape(-1, th.shape[-1])
-        init = StateVector(n, dtype=dtype)
-        es, gs = [], []
-        for row in flat.numpy():
-            e, g = adjoint(init, gates, row, terms)
-            es.append(e)
-            gs.append(g)
+        flat = th.reshape(-1, th.shape[-1]).numpy()
+        P = flat.shape[1]
+        if flat.shape[0] > 1 and all(len(g.qubits) <= 2 for g in gates):
+            # all parameter sets in one batched program
+            b = Batch([gates] * flat.shape[0], [n] * flat.shape[0], [P] * flat.shape[0],
+                      [terms] * flat.shape[0], dtype=dtype)
+            es, gs = b.run(list(flat))
+        else:
+            init = StateVector(n, dtype=dtype)
+            es, gs = [], []
+            for row in flat:
+                e, g = adjoint(init, gates, row, terms)
+                es.append(e)
+                gs.append(g)
         ctx.save_for_backward(torch.tensor(np.array(gs), dtype=theta.dtype).reshape(theta.shape))
-        return torch.tensor(es, dtype=theta.dtype).reshape(theta.shape[:-1]).to(theta.device)
+        return torch.tensor(np.asarray(es), dtype=theta.dtype).reshape(theta.shape[:-1]).to(theta.device)
 
     @staticmethod
     def backward(ctx, grad_out):

@@ -1,0 +1,479 @@
+// Host side of batched adjoint gradients (batch.hpp): builds the op programs
+// of many parametrised circuits, binds parameters into a pinned matrix
+// buffer, and runs the program as per-step launches, per-step launches
+// captured in a hipGraph, or one persistent launch captured in a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "batch.hpp"
+#include "internal.hpp"
+
+namespace cast {
+
+static const cplx kIpowB[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
+
+struct HostOp {
+    uint32_t kind;
+    int gate;            // gate index (FWD/ADJ)
+    int slot;
+};
+
+struct InstPlan {
+    int n;
+    std::vector<cast_gate> gates;          // copied descriptors
+    std::vector<std::vector<cplx>> fixed;  // fixed matrices (sorted-qubit order), per gate
+    std::vector<int> sq0, sq1;             // sorted targets per gate
+    std::vector<uint32_t> xl, zl;          // local generator masks per gate
+    std::vector<uint64_t> gx, gz;          // global generator masks per gate
+    std::vector<int> gslot;                // result slot per gate (-1: none)
+    std::vector<HostOp> ops;
+    std::vector<uint64_t> mat_fwd, mat_adj;  // matrix offsets (complex entries) per gate
+    size_t nparams = 0;
+    int nslots = 0;
+    uint32_t wgs = 1;
+};
+
+}  // namespace cast
+
+struct cast_batch {
+    int ninst = 0;
+    cast_dtype dt = CAST_C128;
+    int mode = 0;
+    hipStream_t stream = nullptr;
+    std::vector<cast::InstPlan> inst;
+    // device
+    void *states = nullptr;
+    cast::BatchRec *d_recs = nullptr;
+    uint64_t *d_step_rec = nullptr, *d_step_item = nullptr;
+    cast::BatchInst *d_insts = nullptr;
+    void *d_mats = nullptr;
+    cast::PauliSumGroup *d_tg = nullptr;
+    cast::PauliSumTerm *d_tt = nullptr;
+    double *d_partials = nullptr, *d_results = nullptr;
+    unsigned long long *d_counters = nullptr;
+    // host
+    void *h_mats = nullptr;      // pinned, matrices in the state dtype
+    double *h_results = nullptr; // pinned
+    size_t mat_entries = 0, result_doubles = 0;
+    std::vector<uint64_t> step_rec, step_item;
+    std::vector<uint64_t> step_items;   // items per step
+    int nsteps = 0;
+    uint64_t total_items = 0;
+    cast::BatchDev dev;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int persistent_grid = 1024;
+};
+
+namespace cast {
+
+static void sorted_matrix(int k, const int *qubits, const std::vector<cplx> &m, int *q0, int *q1,
+                          std::vector<cplx> *out) {
+    PassPlan p;
+    make_plan(k, qubits, m.data(), 0.0, 0.0, &p);
+    *q0 = p.q[0];
+    *q1 = k == 2 ? p.q[1] : -1;
+    *out = p.full;
+}
+
+static void put_matrix(cast_batch *b, uint64_t off, const std::vector<cplx> &m, bool dagger, int k) {
+    const int D = 1 << k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            const cplx z = dagger ? std::conj(m[(size_t)c * D + r]) : m[(size_t)r * D + c];
+            const size_t e = (size_t)(off + (uint64_t)r * D + c);
+            if (b->dt == CAST_C128) {
+                ((double *)b->h_mats)[2 * e] = z.real();
+                ((double *)b->h_mats)[2 * e + 1] = z.imag();
+            } else {
+                ((float *)b->h_mats)[2 * e] = (float)z.real();
+                ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
+            }
+        }
+}
+
+static cast_status queue_program(cast_batch *b) {
+    hipStream_t s = b->stream;
+    const size_t rsz = b->dt == CAST_C128 ? 8 : 4;
+    CAST_HIP_TRY(hipMemcpyAsync(b->d_mats, b->h_mats, b->mat_entries * 2 * rsz, hipMemcpyHostToDevice, s));
+    if (cast_status rc = batch_init_states(b->dev, b->dt, s)) return rc;
+    if (b->mode == 2) {
+        if (cast_status rc = batch_zero(b->d_counters, 2 + (size_t)b->ninst, s)) return rc;
+        if (cast_status rc = batch_launch_persistent(b->dev, b->dt, b->total_items, b->persistent_grid,
+                                                     b->d_counters, 1u << 24, s))
+            return rc;
+    } else {
+        for (int st = 0; st < b->nsteps; ++st)
+            if (cast_status rc = batch_launch_step(b->dev, b->dt, st, b->step_items[st], s)) return rc;
+    }
+    if (cast_status rc = batch_finish(b->dev, s)) return rc;
+    CAST_HIP_TRY(hipMemcpyAsync(b->h_results, b->d_results, b->result_doubles * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    if (b->mode == 2)
+        CAST_HIP_TRY(hipMemcpyAsync(b->h_results + b->result_doubles, b->d_counters + 1, sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, s));
+    return CAST_OK;
+}
+
+static void free_batch(cast_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    dev_free(b->states);
+    dev_free(b->d_recs);
+    dev_free(b->d_step_rec);
+    dev_free(b->d_step_item);
+    dev_free(b->d_insts);
+    dev_free(b->d_mats);
+    dev_free(b->d_tg);
+    dev_free(b->d_tt);
+    dev_free(b->d_partials);
+    dev_free(b->d_results);
+    dev_free(b->d_counters);
+    if (b->h_mats) (void)hipHostFree(b->h_mats);
+    if (b->h_results) (void)hipHostFree(b->h_results);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+template <typename T>
+static cast_status upload(T **dst, const std::vector<T> &src) {
+    if (cast_status rc = dev_alloc((void **)dst, std::max<size_t>(1, src.size()) * sizeof(T))) return rc;
+    if (!src.empty()) CAST_HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CAST_OK;
+}
+
+}  // namespace cast
+
+using namespace cast;
+
+extern "C" {
+
+cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const cast_gate *const *circuits,
+                         const size_t *n_gates, const size_t *n_params, const cast_pauli_term *const *hams,
+                         const size_t *n_terms, const int *init_kind, const cast_sv *const *init_states, int mode,
+                         cast_batch **out) {
+    if (!out) return fail(CAST_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_inst < 1 || n_inst > 65535) return fail(CAST_EINVAL, "n_inst must be in [1, 65535]");
+    if (!n_qubits || !circuits || !n_gates || !n_params || !hams || !n_terms)
+        return fail(CAST_EINVAL, "NULL array argument");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (mode < 0 || mode > 2) return fail(CAST_EINVAL, "mode must be 0, 1 or 2");
+    cast_batch *b = new cast_batch;
+    b->ninst = n_inst;
+    b->dt = dt;
+    b->mode = mode;
+    b->inst.resize(n_inst);
+    std::vector<PauliSumGroup> tg;
+    std::vector<PauliSumTerm> tt;
+    std::vector<BatchInst> hinst(n_inst);
+    size_t state_elems = 0;
+    uint64_t mat_entries = 0, part = 0, res = 0;
+    auto bail = [&](cast_status rc) {
+        free_batch(b);
+        return rc;
+    };
+    for (int i = 0; i < n_inst; ++i) {
+        InstPlan &ip = b->inst[i];
+        const int n = n_qubits[i];
+        if (n < 2 || n > kMaxQubits) return bail(fail(CAST_EINVAL, "instance qubit count must be in [2, 34]"));
+        if (n_gates[i] && !circuits[i]) return bail(fail(CAST_EINVAL, "circuit is NULL"));
+        ip.n = n;
+        ip.nparams = n_params[i];
+        ip.gates.assign(circuits[i], circuits[i] + n_gates[i]);
+        const size_t L = ip.gates.size();
+        ip.fixed.resize(L);
+        ip.sq0.resize(L);
+        ip.sq1.resize(L);
+        ip.xl.assign(L, 0);
+        ip.zl.assign(L, 0);
+        ip.gx.assign(L, 0);
+        ip.gz.assign(L, 0);
+        ip.gslot.assign(L, -1);
+        ip.mat_fwd.resize(L);
+        ip.mat_adj.resize(L);
+        int slot = 1;  // slot 0: energy
+        for (size_t l = 0; l < L; ++l) {
+            const cast_gate &g = ip.gates[l];
+            if (g.k < 1 || g.k > 2) return bail(fail(CAST_EUNSUPPORTED, "batched programs take 1- and 2-qubit gates"));
+            for (int a = 0; a < g.k; ++a) {
+                if (g.qubits[a] < 0 || g.qubits[a] >= n) return bail(fail(CAST_EINVAL, "gate qubit out of range"));
+                for (int c = 0; c < a; ++c)
+                    if (g.qubits[a] == g.qubits[c]) return bail(fail(CAST_EINVAL, "duplicate gate qubit"));
+            }
+            const int D = 1 << g.k;
+            std::vector<cplx> m((size_t)D * D);
+            if (g.param_id >= 0) {
+                if ((size_t)g.param_id >= ip.nparams) return bail(fail(CAST_EINVAL, "param_id out of range"));
+                if (g.generator <= 0 || g.generator >= (1 << (2 * g.k)))
+                    return bail(fail(CAST_EINVAL, "parametrised gate needs a Pauli generator"));
+                m = rotation_matrix(g.k, g.generator, 0.0);  // placeholder; bound in batch_run
+                ip.gslot[l] = slot++;
+            } else {
+                if (!g.matrix) return bail(fail(CAST_EINVAL, "fixed gate without a matrix"));
+                for (int e = 0; e < D * D; ++e) m[e] = cplx(g.matrix[2 * e], g.matrix[2 * e + 1]);
+            }
+            sorted_matrix(g.k, g.qubits, m, &ip.sq0[l], &ip.sq1[l], &ip.fixed[l]);
+            // generator masks: global and in sorted local bits
+            for (int a = 0; a < g.k && g.param_id >= 0; ++a) {
+                const int letter = (g.generator >> (2 * a)) & 3;
+                const int q = g.qubits[a];
+                const int lb = (q == ip.sq0[l]) ? 0 : 1;
+                if (letter == 1 || letter == 2) ip.gx[l] |= 1ull << q, ip.xl[l] |= 1u << lb;
+                if (letter == 2 || letter == 3) ip.gz[l] |= 1ull << q, ip.zl[l] |= 1u << lb;
+            }
+            ip.mat_fwd[l] = mat_entries;
+            mat_entries += (uint64_t)D * D;
+            ip.mat_adj[l] = mat_entries;
+            mat_entries += (uint64_t)D * D;
+        }
+        ip.nslots = slot;
+        for (size_t l = 0; l < L; ++l) ip.ops.push_back(HostOp{BK_FWD, (int)l, -1});
+        ip.ops.push_back(HostOp{BK_HPSI, -1, 0});
+        for (size_t l = L; l-- > 0;) ip.ops.push_back(HostOp{BK_ADJ, (int)l, ip.gslot[l]});
+        ip.wgs = n > 14 ? (1u << (n - 14)) : 1u;
+        // Hamiltonian, grouped by x mask
+        if (n_terms[i] && !hams[i]) return bail(fail(CAST_EINVAL, "Hamiltonian is NULL"));
+        BatchInst &bi = hinst[i];
+        bi.n = n;
+        bi.nslots = ip.nslots;
+        bi.wgs = ip.wgs;
+        bi.tg_off = (uint32_t)tg.size();
+        bi.tt_off = (uint32_t)tt.size();
+        std::map<uint64_t, std::vector<size_t>> byx;
+        std::vector<uint64_t> order;
+        const uint64_t full = (1ull << n) - 1;
+        for (size_t t = 0; t < n_terms[i]; ++t) {
+            const cast_pauli_term &pt = hams[i][t];
+            if ((pt.xmask | pt.zmask) & ~full) return bail(fail(CAST_EINVAL, "Pauli term acts outside the state"));
+            if (!byx.count(pt.xmask)) order.push_back(pt.xmask);
+            byx[pt.xmask].push_back(t);
+        }
+        int first = 0;
+        for (uint64_t x : order) {
+            tg.push_back(PauliSumGroup{x, first, (int)byx[x].size()});
+            for (size_t t : byx[x]) {
+                const cast_pauli_term &pt = hams[i][t];
+                const cplx c = pt.coeff * kIpowB[__builtin_popcountll(pt.xmask & pt.zmask) & 3];
+                tt.push_back(PauliSumTerm{pt.zmask, c.real(), c.imag()});
+                ++first;
+            }
+        }
+        bi.ngroups = (uint32_t)order.size();
+        bi.part_off = part;
+        part += 2ull * ip.nslots * ip.wgs;
+        bi.res_off = res;
+        res += 2ull * ip.nslots;
+        bi.init_kind = init_kind ? init_kind[i] : 0;
+        if (bi.init_kind < 0 || bi.init_kind > 2) return bail(fail(CAST_EINVAL, "bad init kind"));
+        if (bi.init_kind == 2) {
+            const cast_sv *src = init_states ? init_states[i] : nullptr;
+            if (!src || !src->data || src->n != n || src->dt != dt)
+                return bail(fail(CAST_EINVAL, "init state missing or of the wrong size/dtype"));
+            bi.init_src = src->data;
+        }
+        state_elems += 2ull << n;  // psi and lambda
+    }
+    b->mat_entries = mat_entries;
+    b->result_doubles = res;
+    // ---- steps and records
+    size_t max_ops = 0;
+    for (auto &ip : b->inst) max_ops = std::max(max_ops, ip.ops.size());
+    std::vector<BatchRec> recs;
+    b->nsteps = (int)max_ops;
+    uint64_t item_base = 0;
+    for (size_t s = 0; s < max_ops; ++s) {
+        b->step_rec.push_back(recs.size());
+        b->step_item.push_back(item_base);
+        uint64_t items = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            const InstPlan &ip = b->inst[i];
+            if (s >= ip.ops.size()) continue;
+            const HostOp &op = ip.ops[s];
+            BatchRec r;
+            memset(&r, 0, sizeof r);
+            r.kind = op.kind;
+            r.inst = (uint32_t)i;
+            r.item0 = (uint32_t)items;
+            r.wgs = ip.wgs;
+            r.slot = op.slot;
+            r.need = (uint64_t)s * ip.wgs;
+            if (op.kind != BK_HPSI) {
+                const int l = op.gate;
+                r.k = ip.gates[l].k;
+                r.q0 = ip.sq0[l];
+                r.q1 = ip.sq1[l];
+                r.xl = ip.xl[l];
+                r.zl = ip.zl[l];
+                r.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
+                if (op.kind == BK_ADJ && ip.gslot[l] < 0) r.slot = -1;
+            }
+            recs.push_back(r);
+            items += ip.wgs;
+        }
+        if (items > 0x7fffffffull) return bail(fail(CAST_EUNSUPPORTED, "too many work items in one step"));
+        b->step_items.push_back(items);
+        item_base += items;
+    }
+    b->step_rec.push_back(recs.size());
+    b->step_item.push_back(item_base);
+    b->total_items = item_base;
+    // ---- device and pinned buffers
+    const size_t rsz = dt == CAST_C128 ? 8 : 4;
+    const size_t ab = amp_bytes(dt);
+    if (cast_status rc = dev_alloc(&b->states, state_elems * ab)) return bail(rc);
+    size_t off = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const size_t N = (size_t)1 << hinst[i].n;
+        hinst[i].psi = (char *)b->states + off * ab;
+        hinst[i].lam = (char *)b->states + (off + N) * ab;
+        off += 2 * N;
+    }
+    if (cast_status rc = upload(&b->d_recs, recs)) return bail(rc);
+    if (cast_status rc = upload(&b->d_step_rec, b->step_rec)) return bail(rc);
+    if (cast_status rc = upload(&b->d_step_item, b->step_item)) return bail(rc);
+    if (cast_status rc = upload(&b->d_insts, hinst)) return bail(rc);
+    if (cast_status rc = upload(&b->d_tg, tg)) return bail(rc);
+    if (cast_status rc = upload(&b->d_tt, tt)) return bail(rc);
+    if (cast_status rc = dev_alloc(&b->d_mats, std::max<size_t>(1, mat_entries) * 2 * rsz)) return bail(rc);
+    if (cast_status rc = dev_alloc((void **)&b->d_partials, std::max<uint64_t>(1, part) * sizeof(double)))
+        return bail(rc);
+    if (cast_status rc = dev_alloc((void **)&b->d_results, std::max<uint64_t>(1, res) * sizeof(double)))
+        return bail(rc);
+    if (cast_status rc = dev_alloc((void **)&b->d_counters, (2 + (size_t)n_inst) * sizeof(unsigned long long)))
+        return bail(rc);
+    if (hipHostMalloc(&b->h_mats, std::max<size_t>(1, mat_entries) * 2 * rsz) != hipSuccess)
+        return bail(fail(CAST_ENOMEM, "pinned matrix buffer"));
+    if (hipHostMalloc((void **)&b->h_results, (res + 1) * sizeof(double)) != hipSuccess)
+        return bail(fail(CAST_ENOMEM, "pinned result buffer"));
+    for (auto &ip : b->inst)
+        for (size_t l = 0; l < ip.gates.size(); ++l) {
+            put_matrix(b, ip.mat_fwd[l], ip.fixed[l], false, ip.gates[l].k);
+            put_matrix(b, ip.mat_adj[l], ip.fixed[l], true, ip.gates[l].k);
+        }
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(CAST_EHIP, "hipStreamCreate failed"));
+    BatchDev &d = b->dev;
+    d.recs = b->d_recs;
+    d.step_rec = b->d_step_rec;
+    d.step_item = b->d_step_item;
+    d.insts = b->d_insts;
+    d.mats = b->d_mats;
+    d.tg = b->d_tg;
+    d.tt = b->d_tt;
+    d.partials = b->d_partials;
+    d.results = b->d_results;
+    d.nsteps = b->nsteps;
+    d.ninst = n_inst;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->persistent_grid = cus * 4;
+    if (const char *e = std::getenv("CAST_PERSISTENT_WG_PER_CU")) b->persistent_grid = cus * std::max(1, atoi(e));
+    if (mode >= 1) {
+        // capture the whole program once; batch_run refreshes the pinned
+        // matrices and replays it
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bail(fail(CAST_EHIP, "hipStreamBeginCapture failed"));
+        cast_status rc = queue_program(b);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return bail(rc);
+        }
+        if (e != hipSuccess) return bail(fail(CAST_EHIP, std::string("graph capture: ") + hipGetErrorString(e)));
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) return bail(fail(CAST_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e)));
+    }
+    *out = b;
+    return CAST_OK;
+}
+
+cast_status batch_run(cast_batch *b, const double *const *theta, double *energies, double *const *grads) {
+    if (!b) return fail(CAST_EINVAL, "batch is NULL");
+    if (!energies) return fail(CAST_EINVAL, "energies is NULL");
+    for (int i = 0; i < b->ninst; ++i) {
+        const InstPlan &ip = b->inst[i];
+        if (ip.nparams && (!theta || !theta[i] || !grads || !grads[i]))
+            return fail(CAST_EINVAL, "theta/grads missing for an instance with parameters");
+    }
+    // bind parameters (host FP64, cast once into the pinned buffer)
+    for (int i = 0; i < b->ninst; ++i) {
+        const InstPlan &ip = b->inst[i];
+        for (size_t l = 0; l < ip.gates.size(); ++l) {
+            const cast_gate &g = ip.gates[l];
+            if (g.param_id < 0) continue;
+            std::vector<cplx> m = rotation_matrix(g.k, g.generator, g.param_coeff * theta[i][g.param_id]);
+            std::vector<cplx> ms;
+            int q0, q1;
+            sorted_matrix(g.k, g.qubits, m, &q0, &q1, &ms);
+            put_matrix(b, ip.mat_fwd[l], ms, false, g.k);
+            put_matrix(b, ip.mat_adj[l], ms, true, g.k);
+        }
+    }
+    if (b->mode >= 1) {
+        CAST_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        if (cast_status rc = queue_program(b)) return rc;
+    }
+    CAST_HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->mode == 2) {
+        unsigned long long err;
+        memcpy(&err, b->h_results + b->result_doubles, sizeof err);
+        if (err) return fail(CAST_EHIP, "persistent batch: a dependency wait exceeded its bound");
+    }
+    for (int i = 0; i < b->ninst; ++i) {
+        const InstPlan &ip = b->inst[i];
+        size_t off = 0;
+        for (int j = 0; j < i; ++j) off += 2 * (size_t)b->inst[j].nslots;
+        const double *r = b->h_results + off;
+        energies[i] = r[0];
+        if (!ip.nparams) continue;
+        for (size_t p = 0; p < ip.nparams; ++p) grads[i][p] = 0.0;
+        for (size_t l = ip.gates.size(); l-- > 0;) {
+            const int s = ip.gslot[l];
+            if (s < 0) continue;
+            const cplx S(r[2 * s], r[2 * s + 1]);
+            const cplx v = kIpowB[__builtin_popcountll(ip.gx[l] & ip.gz[l]) & 3] * S;
+            grads[i][ip.gates[l].param_id] += ip.gates[l].param_coeff * v.imag();
+        }
+    }
+    return CAST_OK;
+}
+
+void batch_destroy(cast_batch *b) { free_batch(b); }
+
+cast_status adjoint_grad_batch(int n_inst, const int *n_qubits, cast_dtype dt, const cast_gate *const *circuits,
+                               const size_t *n_gates, const double *const *theta, const size_t *n_params,
+                               const cast_pauli_term *const *hams, const size_t *n_terms, const int *init_kind,
+                               const cast_sv *const *init_states, int mode, double *energies, double *const *grads) {
+    cast_batch *b = nullptr;
+    if (cast_status rc = batch_create(n_inst, n_qubits, dt, circuits, n_gates, n_params, hams, n_terms, init_kind,
+                                      init_states, mode, &b))
+        return rc;
+    cast_status rc = batch_run(b, theta, energies, grads);
+    batch_destroy(b);
+    return rc;
+}
+
+cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items, double *state_bytes) {
+    if (!b) return fail(CAST_EINVAL, "batch is NULL");
+    if (n_steps) *n_steps = b->nsteps;
+    if (total_items) *total_items = b->total_items;
+    if (state_bytes) {
+        double s = 0;
+        for (auto &ip : b->inst) s += 2.0 * std::ldexp(1.0, ip.n) * (double)amp_bytes(b->dt);
+        *state_bytes = s;
+    }
+    return CAST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Batched adjoint-gradient programs: many parametrised circuits (same or
+// different qubit counts) evaluated together on one GPU.
+//
+// Each instance's program is a list of ops, op s of every instance forming
+// global step s:
+//   FWD  psi <- U psi                                   (one op per gate)
+//   HPSI lambda <- H psi, partial sums of <psi|lambda>  (energy)
+//   ADJ  partial sums of <lambda|G|psi>, then psi <- U^dag psi, lambda <- U^dag lambda
+// Every op of an instance is split into `wgs` equal work items (one
+// workgroup each); partial sums of item w land in a fixed slot, and a final
+// kernel adds them in a fixed order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "reduce.hpp"
+
+namespace cast {
+
+enum BatchKind : uint32_t { BK_FWD = 0, BK_HPSI = 1, BK_ADJ = 2 };
+
+struct BatchRec {           // op `s` of one instance
+    uint32_t kind;
+    uint32_t inst;
+    uint32_t item0;         // first item of this record within its step
+    uint32_t wgs;           // items (workgroups) of this record
+    int k, q0, q1;          // sorted targets (k <= 2)
+    int slot;               // result slot, or -1
+    uint32_t xl, zl;        // ADJ: generator x/z masks in local (group) index bits
+    uint64_t mat;           // offset (complex entries) of the op's 2^k x 2^k matrix
+    uint64_t need;          // persistent mode: items of this instance that must be done first
+};
+
+struct BatchInst {
+    void *psi;
+    void *lam;
+    int n;
+    int nslots;
+    uint32_t wgs;
+    uint32_t ngroups;       // Pauli-term groups of H
+    uint64_t part_off;      // doubles: partial sums, nslots x wgs x 2
+    uint64_t res_off;       // doubles: results, nslots x 2
+    uint32_t tg_off;        // first PauliSumGroup of H
+    uint32_t tt_off;        // first PauliSumTerm of H (groups' `first` are relative to it)
+    int init_kind;          // 0 |0...0>, 1 |+...+>, 2 copy of init_src
+    int pad;
+    const void *init_src;
+};
+
+struct BatchDev {           // device pointers of one program
+    const BatchRec *recs;   // all records, step-major
+    const uint64_t *step_rec;    // nsteps + 1: first record of each step
+    const uint64_t *step_item;   // nsteps + 1: first global item of each step (persistent mode)
+    const BatchInst *insts;
+    const void *mats;
+    const PauliSumGroup *tg;
+    const PauliSumTerm *tt;
+    double *partials;
+    double *results;
+    int nsteps;
+    int ninst;
+};
+
+// Queues step s (one launch over all its records).
+cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, hipStream_t st);
+// Queues the whole program as one persistent launch: workgroups pull items
+// in global order from a counter; an item waits until its instance has
+// finished the previous op.  Waits are bounded by spin_limit polls; on
+// overrun *err becomes nonzero and every workgroup exits.
+cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
+                                    unsigned long long *counters, uint32_t spin_limit, hipStream_t st);
+// Zeroes `n` 64-bit counters with a kernel (graph-capture safe).
+cast_status batch_zero(unsigned long long *p, size_t n, hipStream_t st);
+// Sets every instance's psi to its initial state (BatchInst::init_kind).
+cast_status batch_init_states(const BatchDev &d, cast_dtype dt, hipStream_t st);
+// Adds each instance's partial sums into results (fixed order).
+cast_status batch_finish(const BatchDev &d, hipStream_t st);
+
+}  // namespace cast

@@ -1,0 +1,325 @@
+// Kernels of the batched adjoint-gradient programs (batch.hpp).
+//
+// One work item = one workgroup's share (1 / wgs) of one op of one instance.
+// The same item routine serves both launch modes: one launch per global step
+// (all instances' op s side by side), or one persistent launch in which
+// workgroups pull items in global order and wait, per instance, for the
+// previous op to finish.
+#include <hip/hip_runtime.h>
+
+#include "batch.hpp"
+#include "internal.hpp"
+
+namespace cast {
+
+template <typename R> struct BAmp;
+template <> struct BAmp<double> { using T = double2; };
+template <> struct BAmp<float> { using T = float2; };
+
+__device__ __forceinline__ uint64_t ins0(uint64_t g, int q) {
+    const uint64_t lm = (1ull << q) - 1;
+    return ((g & ~lm) << 1) | (g & lm);
+}
+
+template <typename V, typename R>
+__device__ __forceinline__ V cmul_acc(V acc, R mr, R mi, V v) {
+    acc.x = fma(mr, v.x, acc.x);
+    acc.x = fma(-mi, v.y, acc.x);
+    acc.y = fma(mr, v.y, acc.y);
+    acc.y = fma(mi, v.x, acc.y);
+    return acc;
+}
+
+// y = M x for a 2^K-vector held in registers (M row-major, uniform).
+template <int K, typename V, typename R>
+__device__ __forceinline__ void small_matvec(const R *m, const V *x, V *y) {
+    constexpr int D = 1 << K;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        V acc;
+        acc.x = 0;
+        acc.y = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc = cmul_acc(acc, m[2 * (r * D + c)], m[2 * (r * D + c) + 1], x[c]);
+        y[r] = acc;
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
+
+// FWD / ADJ over groups [g0, g1) of a K-qubit gate.
+template <int K, typename R>
+__device__ void gate_range(const BatchRec &rec, const BatchInst &in, const R *mats, uint64_t g0, uint64_t g1,
+                           double *pre, double *pim) {
+    using V = typename BAmp<R>::T;
+    constexpr int D = 1 << K;
+    V *psi = reinterpret_cast<V *>(in.psi);
+    V *lam = reinterpret_cast<V *>(in.lam);
+    const R *m = mats + 2 * rec.mat;
+    uint64_t off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        uint64_t o = 0;
+        if (j & 1) o |= 1ull << rec.q0;
+        if (K == 2 && (j & 2)) o |= 1ull << rec.q1;
+        off[j] = o;
+    }
+    double sre = 0.0, sim = 0.0;
+    for (uint64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        uint64_t base = ins0(g, rec.q0);
+        if (K == 2) base = ins0(base, rec.q1);
+        V x[D], y[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = psi[base | off[j]];
+        if (rec.kind == BK_FWD) {
+            small_matvec<K>(m, x, y);
+#pragma unroll
+            for (int j = 0; j < D; ++j) psi[base | off[j]] = y[j];
+        } else {
+            V l[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) l[j] = lam[base | off[j]];
+            if (rec.slot >= 0) {
+                // sum_j conj(lam[j ^ x]) (-1)^{|z & j|} psi[j]: the generator acts inside the group
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const V a = l[j ^ rec.xl];
+                    const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
+                    const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
+                    const bool neg = __popc(rec.zl & (uint32_t)j) & 1;
+                    sre += neg ? -pr : pr;
+                    sim += neg ? -pi : pi;
+                }
+            }
+            small_matvec<K>(m, x, y);
+#pragma unroll
+            for (int j = 0; j < D; ++j) psi[base | off[j]] = y[j];
+            small_matvec<K>(m, l, y);
+#pragma unroll
+            for (int j = 0; j < D; ++j) lam[base | off[j]] = y[j];
+        }
+    }
+    *pre = sre;
+    *pim = sim;
+}
+
+// lambda[y] = (H psi)[y] for y in [y0, y1), and partial <psi|lambda>.
+template <typename R>
+__device__ void hpsi_range(const BatchInst &in, const PauliSumGroup *tg, const PauliSumTerm *tt, uint64_t y0,
+                           uint64_t y1, double *pre, double *pim) {
+    using V = typename BAmp<R>::T;
+    const V *psi = reinterpret_cast<const V *>(in.psi);
+    V *lam = reinterpret_cast<V *>(in.lam);
+    const PauliSumGroup *groups = tg + in.tg_off;
+    const PauliSumTerm *terms = tt + in.tt_off;
+    double sre = 0.0, sim = 0.0;
+    for (uint64_t y = y0 + threadIdx.x; y < y1; y += blockDim.x) {
+        double ar = 0.0, ai = 0.0;
+        for (uint32_t g = 0; g < in.ngroups; ++g) {
+            const uint64_t src = y ^ groups[g].x;
+            const V v = psi[src];
+            double cr = 0.0, ci = 0.0;
+            const int t1 = groups[g].first + groups[g].count;
+            for (int t = groups[g].first; t < t1; ++t) {
+                const bool neg = __popcll(terms[t].z & src) & 1;
+                cr += neg ? -terms[t].cre : terms[t].cre;
+                ci += neg ? -terms[t].cim : terms[t].cim;
+            }
+            ar += cr * (double)v.x - ci * (double)v.y;
+            ai += cr * (double)v.y + ci * (double)v.x;
+        }
+        V o;
+        o.x = (R)ar;
+        o.y = (R)ai;
+        lam[y] = o;
+        const V p = psi[y];
+        // <psi|lambda> with lambda as stored (rounded to the state dtype)
+        sre += (double)p.x * (double)o.x + (double)p.y * (double)o.y;
+        sim += (double)p.x * (double)o.y - (double)p.y * (double)o.x;
+    }
+    *pre = sre;
+    *pim = sim;
+}
+
+// One work item: item w of record rec.
+template <typename R>
+__device__ void run_item(const BatchDev &d, const BatchRec &rec, uint32_t w, double *red) {
+    const BatchInst in = d.insts[rec.inst];
+    const R *mats = reinterpret_cast<const R *>(d.mats);
+    double re = 0.0, im = 0.0;
+    if (rec.kind == BK_HPSI) {
+        const uint64_t N = 1ull << in.n, per = N / rec.wgs;
+        hpsi_range<R>(in, d.tg, d.tt, per * w, per * (w + 1), &re, &im);
+    } else {
+        const uint64_t G = 1ull << (in.n - rec.k), per = G / rec.wgs;
+        if (rec.k == 1) gate_range<1, R>(rec, in, mats, per * w, per * (w + 1), &re, &im);
+        else gate_range<2, R>(rec, in, mats, per * w, per * (w + 1), &re, &im);
+    }
+    if (rec.slot >= 0) {
+        const double sre = block_sum(re, red);
+        const double sim = block_sum(im, red);
+        if (threadIdx.x == 0) {
+            double *p = d.partials + in.part_off + 2 * ((uint64_t)rec.slot * in.wgs + w);
+            p[0] = sre;
+            p[1] = sim;
+        }
+    }
+}
+
+// Largest r in [lo, hi) with recs[r].item0 <= x.
+__device__ __forceinline__ uint64_t find_rec(const BatchRec *recs, uint64_t lo, uint64_t hi, uint64_t x) {
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (recs[mid].item0 <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_batch_step(BatchDev d, int s) {
+    __shared__ double red[4];
+    const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], blockIdx.x);
+    const BatchRec rec = d.recs[r];
+    run_item<R>(d, rec, blockIdx.x - rec.item0, red);
+}
+
+// counters[0]: next item; counters[1]: error flag; counters[2 + i]: items
+// of instance i completed.
+template <typename R>
+__global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t total, unsigned long long *counters,
+                                                          uint32_t spin_limit) {
+    __shared__ double red[4];
+    __shared__ unsigned long long item_sh;
+    __shared__ int stop_sh;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            item_sh = atomicAdd(&counters[0], 1ull);
+            stop_sh = __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        }
+        __syncthreads();
+        const uint64_t item = item_sh;
+        if (item >= total || stop_sh) break;
+        // step of this item, then its record
+        uint64_t lo = 0, hi = (uint64_t)d.nsteps;
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (d.step_item[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int s = (int)lo;
+        const uint64_t x = item - d.step_item[s];
+        const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], x);
+        const BatchRec rec = d.recs[r];
+        if (threadIdx.x == 0) {
+            // wait for the instance's previous op (bounded)
+            unsigned long long *done = &counters[2 + rec.inst];
+            uint32_t spins = 0;
+            while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
+                if (++spins > spin_limit ||
+                    __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    atomicExch(&counters[1], 1ull);
+                    stop_sh = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (stop_sh) break;
+        run_item<R>(d, rec, (uint32_t)(x - rec.item0), red);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&counters[2 + rec.inst], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_zero(unsigned long long *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_batch_init(BatchDev d) {
+    using V = typename BAmp<R>::T;
+    const BatchInst in = d.insts[blockIdx.y];
+    V *psi = reinterpret_cast<V *>(in.psi);
+    const V *src = reinterpret_cast<const V *>(in.init_src);
+    const uint64_t N = 1ull << in.n;
+    const R amp = (R)exp2(-0.5 * in.n);
+    for (uint64_t y = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; y < N; y += (uint64_t)gridDim.x * blockDim.x) {
+        V v;
+        if (in.init_kind == 2) {
+            v = src[y];
+        } else if (in.init_kind == 1) {
+            v.x = amp;
+            v.y = 0;
+        } else {
+            v.x = y == 0 ? (R)1 : (R)0;
+            v.y = 0;
+        }
+        psi[y] = v;
+    }
+}
+
+__global__ void k_batch_finish(BatchDev d) {
+    const BatchInst in = d.insts[blockIdx.x];
+    for (int v = threadIdx.x; v < 2 * in.nslots; v += blockDim.x) {
+        const int slot = v >> 1, c = v & 1;
+        double s = 0.0;
+        for (uint32_t w = 0; w < in.wgs; ++w) s += d.partials[in.part_off + 2 * ((uint64_t)slot * in.wgs + w) + c];
+        d.results[in.res_off + v] = s;
+    }
+}
+
+static cast_status launched(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CAST_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return CAST_OK;
+}
+
+cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, hipStream_t st) {
+    if (dt == CAST_C128) hipLaunchKernelGGL(k_batch_step<double>, dim3((uint32_t)nitems), dim3(256), 0, st, d, s);
+    else hipLaunchKernelGGL(k_batch_step<float>, dim3((uint32_t)nitems), dim3(256), 0, st, d, s);
+    return launched("batched step launch");
+}
+
+cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
+                                    unsigned long long *counters, uint32_t spin_limit, hipStream_t st) {
+    if (dt == CAST_C128)
+        hipLaunchKernelGGL(k_batch_persistent<double>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
+                           spin_limit);
+    else
+        hipLaunchKernelGGL(k_batch_persistent<float>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
+                           spin_limit);
+    return launched("persistent batch launch");
+}
+
+cast_status batch_zero(unsigned long long *p, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(256), 0, st, p, n);
+    return launched("counter reset");
+}
+
+cast_status batch_init_states(const BatchDev &d, cast_dtype dt, hipStream_t st) {
+    if (dt == CAST_C128) hipLaunchKernelGGL(k_batch_init<double>, dim3(1024, d.ninst), dim3(256), 0, st, d);
+    else hipLaunchKernelGGL(k_batch_init<float>, dim3(1024, d.ninst), dim3(256), 0, st, d);
+    return launched("batch init");
+}
+
+cast_status batch_finish(const BatchDev &d, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_finish, dim3(d.ninst), dim3(256), 0, st, d);
+    return launched("batch finish");
+}
+
+}  // namespace cast

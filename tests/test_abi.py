@@ -102,3 +102,18 @@ def test_library_gate_matrices_match_textbook_values():
     np.testing.assert_allclose(ry, [[np.cos(th / 2), -np.sin(th / 2)], [np.sin(th / 2), np.cos(th / 2)]], atol=1e-16)
     u = cast.std_matrix("u3", (np.pi / 2, 0, np.pi))[..., 0]
     np.testing.assert_allclose(u, [[s, s], [s, -s]], atol=1e-15)
+
+
+def test_batch_create_validation():
+    from circuits import hea_vqa, vqa_hamiltonian
+    gates, P = hea_vqa(4, 1)
+    H = vqa_hamiltonian(4)
+    with pytest.raises(cast.CastError):
+        cast.Batch([gates], [1], [P], [H])                          # n < 2
+    with pytest.raises(cast.CastError) as ei:
+        cast.Batch([[Gate("unitary", (0, 1, 2), matrix=np.eye(8))]], [4], [0], [H])
+    assert ei.value.code == -4                                    # 3-qubit gates: unsupported
+    with pytest.raises(cast.CastError):
+        cast.Batch([gates], [4], [P - 1], [H])                      # param_id out of range
+    with pytest.raises(cast.CastError):
+        cast.Batch([gates], [4], [P], [H], mode=5)

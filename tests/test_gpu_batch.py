@@ -1,0 +1,102 @@
+"""Batched adjoint gradients (many parameter sets, mixed qubit counts) on the
+GPU against the oracle's adjoint gradient, per instance."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2503_19894_amd as cast  # noqa: E402
+from circuits import PauliTerm, hea_vqa, tfim_fields, tfim_trotter, vqa_hamiltonian, vqa_thetas  # noqa: E402
+
+MODES = [cast.BATCH_STEPS, cast.BATCH_STEPS_GRAPH, cast.BATCH_PERSISTENT_GRAPH]
+TOL = {torch.complex128: 1e-10, torch.complex64: 5e-4}
+
+
+def vqa_case(n=8, layers=3, sets=5, seed=0):
+    gates, P = hea_vqa(n, layers)
+    return gates, P, vqa_thetas(P, sets, seed=seed), vqa_hamiltonian(n)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["c128", "c64"])
+@pytest.mark.parametrize("mode", MODES, ids=["steps", "graph", "persistent"])
+def test_vqa_batch_vs_oracle(dtype, mode):
+    n = 8
+    gates, P, th, H = vqa_case(n)
+    B = th.shape[0]
+    print(f"vqa batch n={n} B={B} mode={mode} {dtype}", flush=True)
+    b = cast.Batch([gates] * B, [n] * B, [P] * B, [H] * B, dtype=dtype, mode=mode)
+    e, g = b.run(list(th))
+    for i in range(B):
+        ew, gw = oracle.adjoint_grad(n, gates, th[i], H)
+        assert abs(e[i] - ew) <= TOL[dtype], (i, e[i], ew)
+        assert np.max(np.abs(g[i] - gw)) <= TOL[dtype]
+
+
+def test_modes_bitwise_identical_and_replay():
+    n = 9
+    gates, P, th, H = vqa_case(n, layers=2, sets=4, seed=1)
+    B = th.shape[0]
+    outs = []
+    for mode in MODES:
+        b = cast.Batch([gates] * B, [n] * B, [P] * B, [H] * B, mode=mode)
+        outs.append(b.run(list(th)))
+        # replay with other parameters, then the original ones again
+        b.run(list(vqa_thetas(P, B, seed=7)))
+        e2, g2 = b.run(list(th))
+        assert np.array_equal(e2, outs[-1][0])
+        assert all(np.array_equal(x, y) for x, y in zip(g2, outs[-1][1]))
+    for e, g in outs[1:]:
+        assert np.array_equal(e, outs[0][0])
+        assert all(np.array_equal(x, y) for x, y in zip(g, outs[0][1]))
+
+
+@pytest.mark.parametrize("mode", MODES, ids=["steps", "graph", "persistent"])
+def test_mixed_sizes_tfim(mode):
+    ns = [4, 4, 6, 6, 8, 9]
+    circs, fields, obs = [], [], [PauliTerm(1.0, ((0, "Z"),))]
+    for i, n in enumerate(ns):
+        circs.append(tfim_trotter(n, steps=4, dt=0.05))
+        fields.append(tfim_fields(n, seed=i))
+    print(f"mixed tfim mode={mode}", flush=True)
+    b = cast.Batch(circs, ns, ns, [obs] * len(ns), init=["plus"] * len(ns), mode=mode)
+    e, g = b.run(fields)
+    for i, n in enumerate(ns):
+        psi0 = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+        ew, gw = oracle.adjoint_grad(n, circs[i], fields[i], obs, psi0)
+        assert abs(e[i] - ew) <= 1e-11
+        assert np.max(np.abs(g[i] - gw)) <= 1e-11
+
+
+def test_batch_larger_states_cross_workgroups():
+    """n above the single-workgroup size: an op spans several work items."""
+    n = 16
+    gates, P = hea_vqa(n, 1)
+    th = vqa_thetas(P, 2, seed=3)
+    H = vqa_hamiltonian(n)
+    for mode in MODES:
+        b = cast.Batch([gates] * 2, [n] * 2, [P] * 2, [H] * 2, mode=mode)
+        e, g = b.run(list(th))
+        for i in range(2):
+            ew, gw = oracle.adjoint_grad(n, gates, th[i], H)
+            assert abs(e[i] - ew) <= 1e-10
+            assert np.max(np.abs(g[i] - gw)) <= 1e-10
+
+
+def test_init_state_copy():
+    n = 7
+    gates, P, th, H = vqa_case(n, layers=1, sets=2)
+    rng = np.random.default_rng(0)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, device="cuda"))
+    b = cast.Batch([gates] * 2, [n] * 2, [P] * 2, [H] * 2, init=[sv, "zero"])
+    e, g = b.run(list(th))
+    ew, gw = oracle.adjoint_grad(n, gates, th[0], H, psi0)
+    assert abs(e[0] - ew) <= 1e-10 and np.max(np.abs(g[0] - gw)) <= 1e-10
+    ew, gw = oracle.adjoint_grad(n, gates, th[1], H)
+    assert abs(e[1] - ew) <= 1e-10 and np.max(np.abs(g[1] - gw)) <= 1e-10
