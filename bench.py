@@ -16,6 +16,9 @@ written once per pass).  The line also carries:
   cpu_baseline -- the FP64 CPU oracle timed on a bounded sample of the same
                   workload (the first unfused QFT gates on the same 2^30
                   state), in the same unit;
+  vqa_grads_per_s -- batched adjoint VQA gradients/s (20 qubits, 320
+                  parameters, 256 sets) against the plain per-instance
+                  adjoint, both dtypes (details under extras.vqa);
   extras       -- the complex64 run and per-kernel breakdowns.
 """
 import argparse
@@ -96,6 +99,68 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     }
     del sv, psi
     torch.cuda.empty_cache()
+    return out
+
+
+def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_check=True):
+    """Batched VQA gradients (hardware-efficient ansatz, H = sum Z_i Z_i+1 +
+    0.5 sum X_i, parameter sets uniform in [-pi, pi]): grads/s of one batch
+    of `sets` gradients vs the plain per-instance adjoint, both dtypes."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import hea_vqa, vqa_hamiltonian, vqa_thetas
+
+    gates, P = hea_vqa(n, layers)
+    H = vqa_hamiltonian(n)
+    th = vqa_thetas(P, sets, seed=0)
+    out = {"n_qubits": n, "layers": layers, "params": P, "sets": sets, "gates": len(gates)}
+    ref = None
+    for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        res = {}
+        for mname, mode in (("graph", cast.BATCH_STEPS_GRAPH), ("persistent", cast.BATCH_PERSISTENT_GRAPH)):
+            t0 = time.perf_counter()
+            b = cast.Batch([gates] * sets, [n] * sets, [P] * sets, [H] * sets, dtype=dtype, mode=mode)
+            create_s = time.perf_counter() - t0
+            for _ in range(warmup):
+                e, g = b.run(list(th))
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                e, g = b.run(list(th))
+            wall = time.perf_counter() - t0
+            info = b.info()
+            res[mname] = {"grads_per_s": sets * steps / wall, "s_per_batch": wall / steps,
+                          "create_s": round(create_s, 3), "steps": info["steps"],
+                          "state_bytes": info["state_bytes"]}
+            del b
+            torch.cuda.empty_cache()
+        init = cast.StateVector(n, dtype=dtype)
+        cast.adjoint(init, gates, th[0], H)          # warm-up
+        t0 = time.perf_counter()
+        pe, pg = [], []
+        for i in range(plain_sets):
+            ei, gi = cast.adjoint(init, gates, th[i], H)
+            pe.append(ei)
+            pg.append(gi)
+        plain = plain_sets / (time.perf_counter() - t0)
+        best = max(res.values(), key=lambda r: r["grads_per_s"])["grads_per_s"]
+        res["plain"] = {"grads_per_s": plain, "sets_timed": plain_sets}
+        res["batched_vs_plain"] = best / plain
+        # batched and plain agree (different reduction orders)
+        res["batched_plain_max_dgrad"] = float(max(np.max(np.abs(g[i] - pg[i])) for i in range(plain_sets)))
+        if dname == "c128":
+            ref = (e, g)
+        else:
+            res["error_vs_fp64"] = {"energy": float(np.max(np.abs(e - ref[0]))),
+                                    "grad": float(max(np.max(np.abs(a - b)) for a, b in zip(g, ref[1])))}
+        out[dname] = res
+    if oracle_check:
+        import oracle
+        t0 = time.perf_counter()
+        ew, gw = oracle.adjoint_grad(n, gates, th[0], H)
+        out["oracle"] = {"s_per_grad": time.perf_counter() - t0,
+                         "c128_energy_err": abs(ref[0][0] - ew), "c128_grad_err": float(np.max(np.abs(ref[1][0] - gw)))}
     return out
 
 
@@ -215,6 +280,8 @@ def main():
     ap.add_argument("--k-max", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-vqa", action="store_true")
+    ap.add_argument("--vqa-only", action="store_true", help="only the batched VQA measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-kernel-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
@@ -235,6 +302,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.vqa_only:
+        print(json.dumps(run_vqa(oracle_check=False)), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -252,6 +322,7 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    vqa = None if args.no_vqa else run_vqa(oracle_check=not args.no_cpu_baseline)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
     line = {
         "metric": "effective HBM GB/s per fused-gate pass at 30q",
@@ -271,7 +342,12 @@ def main():
                    "state_bytes": (1 << args.n) * 16},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "extras": {"c128": main_run, **extras},
+        "vqa_grads_per_s": None if vqa is None else {
+            "batched_c128": round(max(vqa["c128"]["graph"]["grads_per_s"], vqa["c128"]["persistent"]["grads_per_s"]), 2),
+            "plain_c128": round(vqa["c128"]["plain"]["grads_per_s"], 2),
+            "batched_c64": round(max(vqa["c64"]["graph"]["grads_per_s"], vqa["c64"]["persistent"]["grads_per_s"]), 2),
+            "plain_c64": round(vqa["c64"]["plain"]["grads_per_s"], 2)},
+        "extras": {"c128": main_run, **extras, "vqa": vqa},
     }
     print(json.dumps(line), flush=True)
 

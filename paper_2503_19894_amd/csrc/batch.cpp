@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -28,6 +29,7 @@ struct InstPlan {
     std::vector<std::vector<cplx>> fixed;  // fixed matrices (sorted-qubit order), per gate
     std::vector<int> sq0, sq1;             // sorted targets per gate
     std::vector<uint32_t> xl, zl;          // local generator masks per gate
+    std::vector<int> gen_sorted;           // generator letters in sorted local order
     std::vector<uint64_t> gx, gz;          // global generator masks per gate
     std::vector<int> gslot;                // result slot per gate (-1: none)
     std::vector<HostOp> ops;
@@ -67,6 +69,7 @@ struct cast_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int persistent_grid = 1024;
+    uint32_t persistent_chunk = 16;
 };
 
 namespace cast {
@@ -96,6 +99,44 @@ static void put_matrix(cast_batch *b, uint64_t off, const std::vector<cplx> &m, 
         }
 }
 
+// exp(-i a P / 2) = cos(a/2) I - i sin(a/2) P with P a Pauli string (2-bit
+// letters in local bit order): P has one nonzero per row, at column r ^ x.
+static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double angle, bool dagger) {
+    const int D = 1 << k;
+    const double c = std::cos(angle / 2), s = std::sin(angle / 2) * (dagger ? -1.0 : 1.0);
+    uint32_t x = 0;
+    for (int i = 0; i < k; ++i) {
+        const int L = (gen >> (2 * i)) & 3;
+        if (L == 1 || L == 2) x |= 1u << i;
+    }
+    cplx m[16];
+    for (int e = 0; e < D * D; ++e) m[e] = 0.0;
+    for (int r = 0; r < D; ++r) {
+        // P[r][r ^ x] = prod_i f(letter_i, bit_i(r)); Y: [[0,-i],[i,0]], Z: diag(1,-1)
+        cplx p = 1.0;
+        for (int i = 0; i < k; ++i) {
+            const int L = (gen >> (2 * i)) & 3, bit = (r >> i) & 1;
+            if (L == 2) p *= bit ? cplx(0, 1) : cplx(0, -1);
+            else if (L == 3 && bit) p = -p;
+        }
+        m[r * D + r] += c;
+        m[r * D + (r ^ (int)x)] += cplx(0, -1) * s * p;  // dagger: conj of a Hermitian P's coefficient
+    }
+    // U^dag = cos I + i sin P; the loop above used -s for it, and P is Hermitian
+    for (int r = 0; r < D; ++r)
+        for (int cc = 0; cc < D; ++cc) {
+            const cplx z = m[r * D + cc];
+            const size_t e = (size_t)(off + (uint64_t)r * D + cc);
+            if (b->dt == CAST_C128) {
+                ((double *)b->h_mats)[2 * e] = z.real();
+                ((double *)b->h_mats)[2 * e + 1] = z.imag();
+            } else {
+                ((float *)b->h_mats)[2 * e] = (float)z.real();
+                ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
+            }
+        }
+}
+
 static cast_status queue_program(cast_batch *b) {
     hipStream_t s = b->stream;
     const size_t rsz = b->dt == CAST_C128 ? 8 : 4;
@@ -104,7 +145,7 @@ static cast_status queue_program(cast_batch *b) {
     if (b->mode == 2) {
         if (cast_status rc = batch_zero(b->d_counters, 2 + (size_t)b->ninst, s)) return rc;
         if (cast_status rc = batch_launch_persistent(b->dev, b->dt, b->total_items, b->persistent_grid,
-                                                     b->d_counters, 1u << 24, s))
+                                                     b->d_counters, 1u << 24, b->persistent_chunk, s))
             return rc;
     } else {
         for (int st = 0; st < b->nsteps; ++st)
@@ -174,6 +215,14 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     std::vector<PauliSumTerm> tt;
     std::vector<BatchInst> hinst(n_inst);
     size_t state_elems = 0;
+    // amplitudes per work item, and the cache budget of an instance group
+    int item_log2 = 13;
+    // per-step launches: groups sized for the 256 MB last-level cache; the
+    // persistent launch keeps every instance in one step-major stream
+    double group_bytes = mode == 2 ? 0.0 : 192.0 * (1 << 20);
+    if (const char *e = std::getenv("CAST_BATCH_ITEM_LOG2")) item_log2 = std::max(8, atoi(e));
+    if (const char *e = std::getenv("CAST_BATCH_GROUP_MB"))
+        if (mode != 2) group_bytes = atof(e) * (1 << 20);
     uint64_t mat_entries = 0, part = 0, res = 0;
     auto bail = [&](cast_status rc) {
         free_batch(b);
@@ -193,6 +242,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         ip.sq1.resize(L);
         ip.xl.assign(L, 0);
         ip.zl.assign(L, 0);
+        ip.gen_sorted.assign(L, 0);
         ip.gx.assign(L, 0);
         ip.gz.assign(L, 0);
         ip.gslot.assign(L, -1);
@@ -227,6 +277,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 const int lb = (q == ip.sq0[l]) ? 0 : 1;
                 if (letter == 1 || letter == 2) ip.gx[l] |= 1ull << q, ip.xl[l] |= 1u << lb;
                 if (letter == 2 || letter == 3) ip.gz[l] |= 1ull << q, ip.zl[l] |= 1u << lb;
+                ip.gen_sorted[l] |= letter << (2 * lb);
             }
             ip.mat_fwd[l] = mat_entries;
             mat_entries += (uint64_t)D * D;
@@ -237,7 +288,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         for (size_t l = 0; l < L; ++l) ip.ops.push_back(HostOp{BK_FWD, (int)l, -1});
         ip.ops.push_back(HostOp{BK_HPSI, -1, 0});
         for (size_t l = L; l-- > 0;) ip.ops.push_back(HostOp{BK_ADJ, (int)l, ip.gslot[l]});
-        ip.wgs = n > 14 ? (1u << (n - 14)) : 1u;
+        ip.wgs = n > item_log2 ? (1u << (n - item_log2)) : 1u;
         // Hamiltonian, grouped by x mask
         if (n_terms[i] && !hams[i]) return bail(fail(CAST_EINVAL, "Hamiltonian is NULL"));
         BatchInst &bi = hinst[i];
@@ -282,17 +333,46 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     }
     b->mat_entries = mat_entries;
     b->result_doubles = res;
-    // ---- steps and records
-    size_t max_ops = 0;
-    for (auto &ip : b->inst) max_ops = std::max(max_ops, ip.ops.size());
+    // ---- instance groups (consecutive instances whose psi and lambda fit the
+    // cache budget run their whole programs before the next group), then
+    // steps: step (g, s) holds op s of every instance of group g
+    std::vector<std::pair<int, int>> groups;  // [first, last)
+    {
+        int first = 0;
+        double acc = 0;
+        const double ab_d = (double)amp_bytes(dt);
+        for (int i = 0; i < n_inst; ++i) {
+            const double bytes = 2.0 * std::ldexp(1.0, n_qubits[i]) * ab_d;
+            if (i > first && group_bytes > 0 && acc + bytes > group_bytes) {
+                groups.emplace_back(first, i);
+                first = i;
+                acc = 0;
+            }
+            acc += bytes;
+        }
+        groups.emplace_back(first, n_inst);
+        // keep a captured program below 65536 launches: merge groups if needed
+        size_t max_ops_all = 0;
+        for (auto &ip : b->inst) max_ops_all = std::max(max_ops_all, ip.ops.size());
+        const size_t cap = 65536;
+        if (groups.size() * max_ops_all > cap) {
+            const size_t per = (groups.size() * max_ops_all + cap - 1) / cap;   // groups per merged group
+            std::vector<std::pair<int, int>> merged;
+            for (size_t gi = 0; gi < groups.size(); gi += per)
+                merged.emplace_back(groups[gi].first, groups[std::min(groups.size(), gi + per) - 1].second);
+            groups.swap(merged);
+        }
+    }
     std::vector<BatchRec> recs;
-    b->nsteps = (int)max_ops;
     uint64_t item_base = 0;
+    for (auto &gr : groups) {
+    size_t max_ops = 0;
+    for (int i = gr.first; i < gr.second; ++i) max_ops = std::max(max_ops, b->inst[i].ops.size());
     for (size_t s = 0; s < max_ops; ++s) {
         b->step_rec.push_back(recs.size());
         b->step_item.push_back(item_base);
         uint64_t items = 0;
-        for (int i = 0; i < n_inst; ++i) {
+        for (int i = gr.first; i < gr.second; ++i) {
             const InstPlan &ip = b->inst[i];
             if (s >= ip.ops.size()) continue;
             const HostOp &op = ip.ops[s];
@@ -321,6 +401,8 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         b->step_items.push_back(items);
         item_base += items;
     }
+    }
+    b->nsteps = (int)b->step_items.size();
     b->step_rec.push_back(recs.size());
     b->step_item.push_back(item_base);
     b->total_items = item_base;
@@ -376,6 +458,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     b->persistent_grid = cus * 4;
     if (const char *e = std::getenv("CAST_PERSISTENT_WG_PER_CU")) b->persistent_grid = cus * std::max(1, atoi(e));
+    if (const char *e = std::getenv("CAST_PERSISTENT_CHUNK")) b->persistent_chunk = (uint32_t)std::max(1, atoi(e));
     if (mode >= 1) {
         // capture the whole program once; batch_run refreshes the pinned
         // matrices and replays it
@@ -411,12 +494,9 @@ cast_status batch_run(cast_batch *b, const double *const *theta, double *energie
         for (size_t l = 0; l < ip.gates.size(); ++l) {
             const cast_gate &g = ip.gates[l];
             if (g.param_id < 0) continue;
-            std::vector<cplx> m = rotation_matrix(g.k, g.generator, g.param_coeff * theta[i][g.param_id]);
-            std::vector<cplx> ms;
-            int q0, q1;
-            sorted_matrix(g.k, g.qubits, m, &q0, &q1, &ms);
-            put_matrix(b, ip.mat_fwd[l], ms, false, g.k);
-            put_matrix(b, ip.mat_adj[l], ms, true, g.k);
+            const double a = g.param_coeff * theta[i][g.param_id];
+            bind_rotation(b, ip.mat_fwd[l], g.k, ip.gen_sorted[l], a, false);
+            bind_rotation(b, ip.mat_adj[l], g.k, ip.gen_sorted[l], a, true);
         }
     }
     if (b->mode >= 1) {

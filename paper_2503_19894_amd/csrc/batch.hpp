@@ -70,7 +70,8 @@ cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t 
 // finished the previous op.  Waits are bounded by spin_limit polls; on
 // overrun *err becomes nonzero and every workgroup exits.
 cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
-                                    unsigned long long *counters, uint32_t spin_limit, hipStream_t st);
+                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk,
+                                    hipStream_t st);
 // Zeroes `n` 64-bit counters with a kernel (graph-capture safe).
 cast_status batch_zero(unsigned long long *p, size_t n, hipStream_t st);
 // Sets every instance's psi to its initial state (BatchInst::init_kind).

@@ -194,54 +194,80 @@ __global__ void __launch_bounds__(256) k_batch_step(BatchDev d, int s) {
 }
 
 // counters[0]: next item; counters[1]: error flag; counters[2 + i]: items
-// of instance i completed.
+// of instance i completed.  A workgroup claims `chunk` consecutive items per
+// counter atomic and publishes its completions per run of items of one
+// instance; before any wait it publishes what it holds, so it never waits on
+// its own unpublished work.  Items are claimed in global order and every
+// dependency is on an earlier item, so the earliest unfinished item can
+// always proceed.
 template <typename R>
 __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t total, unsigned long long *counters,
-                                                          uint32_t spin_limit) {
+                                                          uint32_t spin_limit, uint32_t chunk) {
     __shared__ double red[4];
-    __shared__ unsigned long long item_sh;
+    __shared__ unsigned long long base_sh;
     __shared__ int stop_sh;
+    uint32_t pend_inst = 0;     // thread 0 only: completed, unpublished items
+    unsigned long long pend = 0;
     for (;;) {
         if (threadIdx.x == 0) {
-            item_sh = atomicAdd(&counters[0], 1ull);
+            base_sh = atomicAdd(&counters[0], (unsigned long long)chunk);
             stop_sh = __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         }
         __syncthreads();
-        const uint64_t item = item_sh;
-        if (item >= total || stop_sh) break;
-        // step of this item, then its record
-        uint64_t lo = 0, hi = (uint64_t)d.nsteps;
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) / 2;
-            if (d.step_item[mid] <= item) lo = mid;
-            else hi = mid;
-        }
-        const int s = (int)lo;
-        const uint64_t x = item - d.step_item[s];
-        const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], x);
-        const BatchRec rec = d.recs[r];
-        if (threadIdx.x == 0) {
-            // wait for the instance's previous op (bounded)
-            unsigned long long *done = &counters[2 + rec.inst];
-            uint32_t spins = 0;
-            while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
-                if (++spins > spin_limit ||
-                    __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    atomicExch(&counters[1], 1ull);
-                    stop_sh = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+        const uint64_t base = base_sh;
+        if (base >= total || stop_sh) break;
+        const uint64_t end = base + chunk < total ? base + chunk : total;
+        for (uint64_t item = base; item < end; ++item) {
+            uint64_t lo = 0, hi = (uint64_t)d.nsteps;
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (d.step_item[mid] <= item) lo = mid;
+                else hi = mid;
             }
+            const int s = (int)lo;
+            const uint64_t x = item - d.step_item[s];
+            const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], x);
+            const BatchRec rec = d.recs[r];
+            if (threadIdx.x == 0) {
+                unsigned long long *done = &counters[2 + rec.inst];
+                if (pend && pend_inst != rec.inst) {
+                    __hip_atomic_fetch_add(&counters[2 + pend_inst], pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    pend = 0;
+                }
+                if (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
+                    if (pend) {
+                        __hip_atomic_fetch_add(done, pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        pend = 0;
+                    }
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
+                        if (++spins > spin_limit ||
+                            __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            atomicExch(&counters[1], 1ull);
+                            stop_sh = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+            }
+            __syncthreads();
+            if (stop_sh) break;
+            run_item<R>(d, rec, (uint32_t)(x - rec.item0), red);
+            // the barrier makes every wave's stores visible to the workgroup;
+            // thread 0's agent-scope release later publishes them device-wide
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                pend_inst = rec.inst;
+                ++pend;
+            }
+        }
+        if (threadIdx.x == 0 && pend) {
+            __hip_atomic_fetch_add(&counters[2 + pend_inst], pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            pend = 0;
         }
         __syncthreads();
         if (stop_sh) break;
-        run_item<R>(d, rec, (uint32_t)(x - rec.item0), red);
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&counters[2 + rec.inst], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
     }
 }
 
@@ -296,13 +322,14 @@ cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t 
 }
 
 cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
-                                    unsigned long long *counters, uint32_t spin_limit, hipStream_t st) {
+                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk,
+                                    hipStream_t st) {
     if (dt == CAST_C128)
         hipLaunchKernelGGL(k_batch_persistent<double>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
-                           spin_limit);
+                           spin_limit, chunk);
     else
         hipLaunchKernelGGL(k_batch_persistent<float>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
-                           spin_limit);
+                           spin_limit, chunk);
     return launched("persistent batch launch");
 }
 
