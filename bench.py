@@ -37,6 +37,10 @@ def kernel_label(info, dtype_name):
     r = "double" if dtype_name == "c128" else "float"
     if kind == 3:
         return f"k_diag<{r}, 4>"
+    if kind == 4:
+        return f"k_mfma_direct<{info['d']}, {r}>"
+    if kind == 5:
+        return f"k_mfma_tile<{info['d']}, {r}>"
     if kind == 0:
         return f"k_direct<{info['d']}, {r}>"
     uni = "true"  # tiles hold >= 64 groups at n = 30
@@ -100,6 +104,51 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     del sv, psi
     torch.cuda.empty_cache()
     return out
+
+
+def run_dense(n=32, depth=20, steps=1, warmup=1):
+    """Dense random circuit (20 layers of Haar gates on 6- and 5-qubit random
+    subsets, complex128, from |0...0>): per-pass kernel throughput; dense
+    6-qubit passes are FP64-compute-bound, 5-qubit passes HBM-bound."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import dense_haar_layers
+
+    gates = dense_haar_layers(n, depth, seed=0)
+    fc = cast.FusedCircuit(n, gates, k_max=6)
+    infos = [fc.pass_info(i, torch.complex128) for i in range(len(fc))]
+    psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+    psi[0] = 1
+    sv = cast.StateVector(n, tensor=psi)
+    for _ in range(warmup):
+        sv.apply_circuit(fc)
+    torch.cuda.synchronize()
+    per = np.zeros(len(fc))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per += sv.apply_circuit_timed(fc)
+    wall = time.perf_counter() - t0
+    per /= steps
+    kern = {}
+    for inf, ms in zip(infos, per):
+        lab = kernel_label(inf, "c128")
+        k = kern.setdefault(lab, {"launches": 0, "ms": 0.0, "alg_bytes": 0.0, "flops": 0.0})
+        k["launches"] += 1
+        k["ms"] += float(ms)
+        k["alg_bytes"] += inf["alg_bytes"]
+        k["flops"] += inf["flops"]
+    for k in kern.values():
+        k["achieved_gbs"] = k["alg_bytes"] / (k["ms"] * 1e-3) / 1e9
+        k["achieved_tflops"] = k["flops"] / (k["ms"] * 1e-3) / 1e12
+    nrm = float(torch.linalg.vector_norm(psi))
+    del sv, psi
+    torch.cuda.empty_cache()
+    return {"n_qubits": n, "passes": len(fc), "s_per_circuit": wall / steps,
+            "event_s_per_circuit": float(per.sum()) / 1e3, "norm_after": nrm, "kernels": kern,
+            "fp64_roof_s": sum(i["flops"] for i in infos) / 78.6e12,
+            "hbm_roof_s": sum(i["alg_bytes"] for i in infos) / 8e12}
 
 
 def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_check=True):
@@ -282,6 +331,8 @@ def main():
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-vqa", action="store_true")
     ap.add_argument("--vqa-only", action="store_true", help="only the batched VQA measurement")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--dense-only", action="store_true", help="only the 32-qubit dense circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-kernel-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
@@ -302,6 +353,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.dense_only:
+        print(json.dumps(run_dense()), flush=True)
+        return
     if args.vqa_only:
         print(json.dumps(run_vqa(oracle_check=False)), flush=True)
         return
@@ -323,6 +377,7 @@ def main():
             "traffic": traffic, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
     vqa = None if args.no_vqa else run_vqa(oracle_check=not args.no_cpu_baseline)
+    dense = None if args.no_dense else run_dense()
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
     line = {
         "metric": "effective HBM GB/s per fused-gate pass at 30q",
@@ -347,7 +402,7 @@ def main():
             "plain_c128": round(vqa["c128"]["plain"]["grads_per_s"], 2),
             "batched_c64": round(max(vqa["c64"]["graph"]["grads_per_s"], vqa["c64"]["persistent"]["grads_per_s"]), 2),
             "plain_c64": round(vqa["c64"]["plain"]["grads_per_s"], 2)},
-        "extras": {"c128": main_run, **extras, "vqa": vqa},
+        "extras": {"c128": main_run, **extras, "vqa": vqa, "dense32": dense},
     }
     print(json.dumps(line), flush=True)
 

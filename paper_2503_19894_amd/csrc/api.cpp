@@ -37,6 +37,11 @@ Tuning &tuning() {
         env("CAST_DIRECT_IPT", x.direct_ipt);
         env("CAST_DIRECT_NT", x.direct_nt);
         env("CAST_USE_DIAG", x.use_diag);
+        env("CAST_MFMA_MIN_D_C64", x.mfma_min_d[CAST_C64]);
+        env("CAST_MFMA_MIN_D_C128", x.mfma_min_d[CAST_C128]);
+        env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
+        env("CAST_MFMA_DIRECT_MIN_Q_C64", x.mfma_direct_min_q[CAST_C64]);
+        env("CAST_MFMA_DIRECT_MIN_Q_C128", x.mfma_direct_min_q[CAST_C128]);
         return x;
     }();
     return t;

@@ -379,6 +379,187 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
     }
 }
 
+// ------------------------------------------------------------------ MFMA
+// Dense blocks (d >= 4) as complex GEMMs on the matrix cores: a wave takes 16
+// groups of one block and computes all 2^d output rows as 16 x 16 tiles,
+//   Yr += Ur Xr - Ui Xi,  Yi += Ur Xi + Ui Xr,
+// four real 16x16x4 MFMAs per k-step (FP64 for complex128, FP32 for
+// complex64).  Operand lane layouts (checked on gfx950): lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result value v of lane l is
+// D[row][l % 16] with row = l / 16 + 4 v (f64) or 4 (l / 16) + v (f32).
+// The active blocks' matrices are staged transposed in LDS (lanes with
+// consecutive rows read consecutive entries).  A wave reads all inputs of its
+// 16 groups before writing any output, so updates are in place.
+typedef double mf_v4d __attribute__((ext_vector_type(4)));
+typedef float mf_v4f __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+    using acc = mf_v4d;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Mfma<float> {
+    using acc = mf_v4f;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Stages the active blocks' matrices transposed: mt[(b * N + c) * N + i] = M_b[i][c].
+template <int D, typename V, typename R>
+__device__ __forceinline__ void stage_blocks(V *mt, const R *mat, uint32_t nblk) {
+    constexpr int N = 1 << D;
+    for (uint32_t e = threadIdx.x; e < nblk * N * N; e += blockDim.x) {
+        const uint32_t b = e / (N * N), rem = e % (N * N), i = rem / N, c = rem % N;
+        V v;
+        v.x = mat[2 * e];
+        v.y = mat[2 * e + 1];
+        mt[(b * N + c) * N + i] = v;
+    }
+}
+
+// One unit: 16 groups of block slot bs.  load(c) returns X[c][group lane%16]
+// (this lane's k-row c); store(row, value) writes Y[row][group lane%16].
+template <int D, typename R, typename Load, typename Store>
+__device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load load, Store store) {
+    using V = typename Amp<R>::T;
+    using M = Mfma<R>;
+    constexpr int N = 1 << D, T = N / 16;
+    const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+    typename M::acc cr[T], ci[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cr[t][v] = ci[t][v] = 0;
+    }
+#pragma unroll 4
+    for (int s = 0; s < N / 4; ++s) {
+        const int c = 4 * s + kk;
+        const V x = load(c);
+        const V *col = mt_blk + c * N + j;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const V u = col[16 * t];
+            cr[t] = M::mma(u.x, x.x, cr[t]);
+            cr[t] = M::mma(-u.y, x.y, cr[t]);
+            ci[t] = M::mma(u.x, x.y, ci[t]);
+            ci[t] = M::mma(u.y, x.x, ci[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            V y;
+            y.x = cr[t][v];
+            y.y = ci[t][v];
+            store(16 * t + M::row(lane, v), y);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t off_of(const uint64_t *off, int c) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+        if ((c >> b) & 1) o ^= off[b];
+    return o;
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, const R *__restrict__ mat, PassArgs a) {
+    using V = typename Amp<R>::T;
+    constexpr int N = 1 << D;
+    extern __shared__ uint4 lds_raw[];
+    V *mt = reinterpret_cast<V *>(lds_raw);
+    V *psi = reinterpret_cast<V *>(psi_r);
+    stage_blocks<D>(mt, mat, a.nblk);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15;
+    const uint64_t upb = a.ngroups >> 4;   // units per block
+    const uint64_t units = upb * a.nblk;
+    for (uint64_t u = (uint64_t)blockIdx.x * 4 + wave; u < units; u += (uint64_t)gridDim.x * 4) {
+        const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(u / upb));
+        const uint64_t g = (u % upb) * 16 + j;
+        const uint32_t bid = a.blk[bs];
+        uint64_t base = deposit(g, a.lowmask, a.k);
+        for (int q = 0; q < a.k - D; ++q)
+            if ((bid >> q) & 1u) base ^= a.off[D + q];
+        mfma_unit<D, R>(
+            mt + (size_t)bs * N * N, [&](int c) { return psi[base ^ off_of<D>(a.off, c)]; },
+            [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; });
+    }
+}
+
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_mfma_tile(R *__restrict__ psi_r, const R *__restrict__ mat, PassArgs a) {
+    using V = typename Amp<R>::T;
+    constexpr int N = 1 << D;
+    constexpr int S = sizeof(V) == 16 ? 0 : 1;
+    extern __shared__ uint4 lds_raw[];
+    V *mt = reinterpret_cast<V *>(lds_raw);
+    const size_t mt_elems = (size_t)a.nblk * N * N;
+    uint4 *tile16 = lds_raw + (mt_elems * sizeof(V)) / 16;
+    V *tile = reinterpret_cast<V *>(tile16);
+    const uint4 *src16 = reinterpret_cast<const uint4 *>(psi_r);
+    uint4 *dst16 = reinterpret_cast<uint4 *>(psi_r);
+    stage_blocks<D>(mt, mat, a.nblk);
+    const uint32_t tile_amps = 1u << a.tb;
+    const uint32_t chunks = tile_amps >> S;
+    const uint32_t rcl = a.W - S;
+    const uint32_t log_gt = a.tb - a.k;
+    const uint32_t upb = (1u << log_gt) >> 4;   // units per block in a tile
+    const uint32_t units = upb * a.nblk;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15;
+    for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+        const uint64_t tbase = deposit(t << a.W, a.hilowmask, a.khi);
+        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
+            uint4 buf[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) buf[u] = src16[tile_chunk_addr(c0 + u * 256, tbase, rcl, S, a)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tile16[swz(c0 + u * 256)] = buf[u];
+        }
+        __syncthreads();
+        for (uint32_t u = wave; u < units; u += 4) {
+            const uint32_t bs = u / upb;
+            const uint32_t gl = (u % upb) * 16 + j;
+            const uint32_t bid = a.blk[bs];
+            uint32_t pos = gl;
+            for (int i = 0; i < a.klo; ++i) {
+                const uint32_t lm = a.tlowmask[i];
+                pos = ((pos & ~lm) << 1) | (pos & lm);
+            }
+            for (int q = 0; q < a.k - D; ++q)
+                if ((bid >> q) & 1u) pos ^= a.toff[D + q];
+            auto toff_of = [&](int c) {
+                uint32_t o = 0;
+#pragma unroll
+                for (int b = 0; b < D; ++b)
+                    if ((c >> b) & 1) o ^= a.toff[b];
+                return o;
+            };
+            mfma_unit<D, R>(
+                mt + (size_t)bs * N * N, [&](int c) { return tile[lds_elem<S>(pos ^ toff_of(c))]; },
+                [&](int row, const V &y) { tile[lds_elem<S>(pos ^ toff_of(row))] = y; });
+        }
+        __syncthreads();
+        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
+            uint4 buf[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) buf[u] = tile16[swz(c0 + u * 256)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dst16[tile_chunk_addr(c0 + u * 256, tbase, rcl, S, a)] = buf[u];
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ dispatch
 template <int DD, typename R, int IPT, bool NT>
 static void launch_one(R *psi, const R *m, const PassArgs &a, int grid, hipStream_t s) {
@@ -469,9 +650,64 @@ static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 5; }
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p) {
     const Tuning &tu = tuning();
     if (p.d == 0 && tu.use_diag) return 3;
+    if (p.d >= tu.mfma_min_d[dt] && mfma_fits(n, dt, p)) {
+        if (p.q[0] >= tu.mfma_direct_min_q[dt] && (n - p.k) >= 4) return 4;
+        return 5;
+    }
     if (p.d > max_reg_d(dt)) return 2;
     if (p.q[0] >= tu.direct_min_q[dt] && (n - p.k) >= 6) return 0;
     return 1;
+}
+
+// LDS bytes of the staged block matrices, and the MFMA tile size.
+static size_t mfma_mat_bytes(cast_dtype dt, const PassPlan &p) {
+    return p.blk.size() * ((size_t)1 << (2 * p.d)) * amp_bytes(dt);
+}
+static int mfma_tile_bits(int n, cast_dtype dt, const PassPlan &p) {
+    // tile + matrices within 128 KiB; a tile holds at least 16 groups
+    int tb = tuning().tile_bits[dt];
+    while (tb > p.k + 4 && ((size_t)1 << tb) * amp_bytes(dt) + mfma_mat_bytes(dt, p) > (128u << 10)) --tb;
+    return tb > n ? n : tb;
+}
+bool mfma_fits(int n, cast_dtype dt, const PassPlan &p) {
+    if (p.d < 4 || n - p.k < 4) return false;
+    if (mfma_mat_bytes(dt, p) > (64u << 10)) return false;
+    const int tb = mfma_tile_bits(n, dt, p);
+    return tb >= p.k + 4 && ((size_t)1 << tb) * amp_bytes(dt) + mfma_mat_bytes(dt, p) <= (128u << 10) &&
+           ((size_t)1 << tb) / (16 / amp_bytes(dt)) >= 8 * 256;
+}
+
+template <typename R>
+static hipError_t launch_mfma(int D, bool tile, R *psi, const R *m, const PassArgs &a, int grid, size_t lds,
+                              hipStream_t s) {
+#define CAST_MFMA(DD)                                                                                    \
+    case DD:                                                                                             \
+        if (tile) {                                                                                      \
+            static bool set = false;                                                                     \
+            if (!set) {                                                                                  \
+                hipError_t e = hipFuncSetAttribute((const void *)k_mfma_tile<DD, R>,                     \
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10); \
+                if (e != hipSuccess) return e;                                                           \
+                set = true;                                                                              \
+            }                                                                                            \
+            hipLaunchKernelGGL((k_mfma_tile<DD, R>), dim3(grid), dim3(256), lds, s, psi, m, a);          \
+        } else {                                                                                         \
+            static bool set = false;                                                                     \
+            if (!set) {                                                                                  \
+                hipError_t e = hipFuncSetAttribute((const void *)k_mfma_direct<DD, R>,                   \
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10); \
+                if (e != hipSuccess) return e;                                                           \
+                set = true;                                                                              \
+            }                                                                                            \
+            hipLaunchKernelGGL((k_mfma_direct<DD, R>), dim3(grid), dim3(256), lds, s, psi, m, a);        \
+        }                                                                                                \
+        break;
+    switch (D) {
+        CAST_MFMA(4) CAST_MFMA(5) CAST_MFMA(6)
+        default: return hipErrorInvalidValue;
+    }
+#undef CAST_MFMA
+    return hipGetLastError();
 }
 
 cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
@@ -495,7 +731,51 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
     const bool twobuf = kind == 2;
     const bool direct = kind == 0;
     hipError_t e;
-    if (kind == 3) {
+    if (kind == 4 || kind == 5) {
+        for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
+        a.log_ngroups = n - k;
+        a.ngroups = 1ull << (n - k);
+        size_t lds = mfma_mat_bytes(dt, p);
+        uint64_t grid;
+        if (kind == 4) {
+            const uint64_t units = (a.ngroups >> 4) * a.nblk;
+            grid = (units + 3) / 4;
+            const uint64_t cap = (uint64_t)tu.mfma_grid_per_cu * 256;
+            if (grid > cap) grid = cap;
+        } else {
+            const int tb = mfma_tile_bits(n, dt, p);
+            int khi = 0;
+            for (;; ++khi) {
+                int cnt = 0;
+                for (int i = 0; i < k; ++i) cnt += p.q[i] >= tb - khi;
+                if (cnt == khi) break;
+            }
+            const int W = tb - khi;
+            a.tb = tb;
+            a.W = W;
+            a.khi = khi;
+            a.klo = k - khi;
+            for (int j = 0; j < khi; ++j) {
+                a.qhi[j] = p.q[a.klo + j];
+                a.hilowmask[j] = (1ull << a.qhi[j]) - 1;
+            }
+            for (int i = 0; i < a.klo; ++i) a.tlowmask[i] = (1u << p.q[i]) - 1;
+            for (int i = 0; i < k; ++i) {
+                uint32_t o = 0;
+                for (int s2 = 0; s2 < k; ++s2)
+                    if ((p.L[i] >> s2) & 1u) o |= (s2 < a.klo) ? (1u << p.q[s2]) : (1u << (W + s2 - a.klo));
+                a.toff[i] = o;
+            }
+            a.ntiles = 1ull << (n - tb);
+            grid = a.ntiles;
+            if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
+            lds += ((size_t)1 << tb) * amp_bytes(dt);
+        }
+        if (dt == CAST_C128)
+            e = launch_mfma<double>(D, kind == 5, (double *)psi, (const double *)dmat, a, (int)grid, lds, stream);
+        else
+            e = launch_mfma<float>(D, kind == 5, (float *)psi, (const float *)dmat, a, (int)grid, lds, stream);
+    } else if (kind == 3) {
         DiagArgs g;
         memset(&g, 0, sizeof g);
         g.k = k;

@@ -70,12 +70,16 @@ struct Tuning {                      // launch parameters chosen per (dtype, ker
     int direct_ipt = 4;              // work items per thread per iteration (capped by registers)
     int direct_nt = 1;               // non-temporal loads/stores in the direct kernel
     int use_diag = 1;                // elementwise kernel for diagonal passes
+    int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels, by dtype
+    int mfma_grid_per_cu = 4;        // MFMA direct kernel: workgroups per CU
+    int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather, by dtype
     int max_grid = 1 << 20;
 };
 Tuning &tuning();
 
 // Kernel a pass uses: 0 direct, 1 LDS tile, 2 LDS tile with two buffers,
-// 3 elementwise diagonal.
+// 3 elementwise diagonal, 4 MFMA direct, 5 MFMA tile.
+bool mfma_fits(int n, cast_dtype dt, const PassPlan &p);
 // Device layout of a plan's matrices (reals of the state dtype): the active
 // blocks, or for diagonal plans (d = 0) the full diagonal of 2^k entries.
 template <typename R>

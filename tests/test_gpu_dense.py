@@ -1,0 +1,70 @@
+"""Dense random circuits (Haar gates on 6- and 5-qubit random subsets, the
+MFMA path): full oracle comparison at 22 qubits with the same generator, and
+at 32 qubits (complex128, 64 GiB) the product-state closed form after the
+first layer plus the circuit-inverse round trip."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import paper_2503_19894_amd as cast  # noqa: E402
+from circuits import Gate, dense_haar_layers, random_state  # noqa: E402
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
+def test_dense_haar_22_vs_oracle(dtype, tol):
+    n = 22
+    gates = dense_haar_layers(n, depth=4, seed=1)
+    psi0 = random_state(n, seed=1, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+    fc = cast.FusedCircuit(n, gates, k_max=6)
+    kinds = {fc.pass_info(i, dtype)["kernel"] for i in range(len(fc))}
+    print(f"dense22 {dtype}: kernels {sorted(kinds)}", flush=True)
+    assert kinds & {4, 5}, "expected the MFMA kernels"
+    sv.apply_circuit(fc)
+    err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    print(f"  max |d amp| = {err:.2e}", flush=True)
+    assert err <= tol
+
+
+def _column0(g):
+    return np.asarray(g.matrix, dtype=np.complex128)[:, 0]
+
+
+def test_dense_haar_32_first_layer_and_inverse():
+    n = 32
+    gates = dense_haar_layers(n, depth=20, seed=0)
+    first = gates[:6]
+    assert sorted(q for g in first for q in g.qubits) == list(range(n))
+    psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+    psi[0] = 1
+    sv = cast.StateVector(n, tensor=psi)
+    print("dense32: first layer", flush=True)
+    sv.apply_circuit(cast.FusedCircuit(n, first, k_max=6))
+    torch.cuda.synchronize()
+    # product state: amp(x) = prod over gates of U_g[j_g(x)][0], j_g(x) = bits of x on the gate's qubits
+    rng = np.random.default_rng(32)
+    xs = [0, (1 << n) - 1] + [int(v) for v in rng.integers(0, 1 << n, 30)]
+    got = psi[torch.tensor(xs, device="cuda")].cpu().numpy()
+    for x, a in zip(xs, got):
+        want = 1.0 + 0j
+        for g in first:
+            j = sum(((x >> q) & 1) << i for i, q in enumerate(g.qubits))
+            want *= _column0(g)[j]
+        assert abs(a - want) <= 1e-13, (x, a, want)
+    print("dense32: remaining layers and the inverse", flush=True)
+    sv.apply_circuit(cast.FusedCircuit(n, gates[6:], k_max=6))
+    inv = [Gate("unitary", g.qubits, matrix=np.asarray(g.matrix).conj().T) for g in reversed(gates)]
+    sv.apply_circuit(cast.FusedCircuit(n, inv, k_max=6))
+    torch.cuda.synchronize()
+    err0 = abs(complex(psi[0].item()) - 1.0)
+    psi[0] = 0
+    rest = float(psi.abs().max())
+    print(f"  |psi[0] - 1| = {err0:.2e}, max |other| = {rest:.2e}", flush=True)
+    assert err0 <= 1e-12 and rest <= 1e-12
