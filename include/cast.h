@@ -128,10 +128,11 @@ typedef struct {
     int agglomerative;    /* grow the size limit 2 .. k_max (else k_max at once) */
     int multi_traversal;  /* repeat each traversal until nothing fuses */
     int cost_model;       /* 0: size-only; 1: adaptive (tuned cost table) */
+    int cost_dtype;       /* dtype whose cost table the adaptive check uses (0 = CAST_C128) */
 } cast_fusion_opts;
 
 /* Default options: k_max 5, no cap, tolerances 1e-14, agglomerative and
- * multi-traversal on, size-only. */
+ * multi-traversal on, size-only, complex128 cost table. */
 void fusion_opts_default(cast_fusion_opts *opts);
 
 /* Fuses a circuit of fixed gates (param_id must be -1; parametrised gates are
@@ -177,6 +178,29 @@ cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt,
 /* Frees a fused list.  NULL-safe.  The caller must not destroy a list while
  * work that uses it is still queued (synchronise the stream first). */
 void fused_destroy(cast_fused *f);
+
+/* ------------------------------------------------------------ tuning */
+
+/* Launch knobs of the pass kernels, per dtype (dt = CAST_C64 or CAST_C128;
+ * ignored for dtype-independent keys).  Keys: "direct_min_q" (smallest
+ * target for the direct gather), "tile_bits" (log2 amplitudes per LDS tile),
+ * "direct_ipt" (work items per thread: 1, 2 or 4), "direct_nt" (non-temporal
+ * hints 0/1), "max_grid" (workgroup cap), "use_diag" (elementwise diagonal
+ * kernel 0/1), "mfma_min_d" (smallest block dimension for the matrix cores,
+ * 4..7; 7 disables them), "mfma_grid_per_cu", "mfma_direct_min_q".
+ * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
+ * against concurrent launches: set knobs before queuing work. */
+cast_status tuning_set(const char *key, cast_dtype dt, int value);
+cast_status tuning_get(const char *key, cast_dtype dt, int *value);
+
+/* Predicted time of one pass of a k-qubit gate with block dimension d over
+ * 2^n amplitudes, in milliseconds per 2^30 amplitudes, used by the adaptive
+ * fusibility check (cost_model = 1): a fusion is accepted only if the fused
+ * pass is predicted no slower than the two passes it replaces (Sec. III-C).
+ * Entries start at an HBM-bound estimate and are replaced by the autotuner's
+ * measurements. */
+cast_status cost_table_set(cast_dtype dt, int k, int d, double ms_per_gamp);
+cast_status cost_table_get(cast_dtype dt, int k, int d, double *ms_per_gamp);
 
 /* ------------------------------------------------------------ observables */
 

@@ -40,7 +40,7 @@ class cast_gate(ctypes.Structure):
 class cast_fusion_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int), ("opcount_cap", ctypes.c_double), ("zero_tol", ctypes.c_double),
                 ("one_tol", ctypes.c_double), ("agglomerative", ctypes.c_int), ("multi_traversal", ctypes.c_int),
-                ("cost_model", ctypes.c_int)]
+                ("cost_model", ctypes.c_int), ("cost_dtype", ctypes.c_int)]
 
 
 class cast_pauli_term(ctypes.Structure):
@@ -84,6 +84,10 @@ SIGNATURES = {
                                  ctypes.POINTER(_c_double_p)]),
     "batch_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_uint64), _c_double_p]),
     "batch_destroy": (None, [ctypes.c_void_p]),
+    "tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]),
+    "tuning_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _c_int_p]),
+    "cost_table_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+    "cost_table_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p]),
     "adjoint_grad_batch": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.c_int,
                                           ctypes.POINTER(ctypes.POINTER(cast_gate)), ctypes.POINTER(ctypes.c_size_t),
                                           ctypes.POINTER(_c_double_p), ctypes.POINTER(ctypes.c_size_t),
@@ -101,7 +105,7 @@ for _name, (_res, _args) in SIGNATURES.items():
     _f.argtypes = _args
 
 
-class CastError(RuntimeError):
+class CastError(RuntimeError):  # noqa: E302
     def __init__(self, code, msg):
         super().__init__(f"libcast error {code}: {msg}")
         self.code = code
@@ -198,11 +202,51 @@ def pauli_terms(terms):
 
 
 def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, agglomerative=True,
-                   multi_traversal=True, cost_model=0):
+                   multi_traversal=True, cost_model=0, cost_dtype=None):
     o = cast_fusion_opts()
     o.k_max, o.opcount_cap, o.zero_tol, o.one_tol = k_max, opcount_cap, zero_tol, one_tol
     o.agglomerative, o.multi_traversal, o.cost_model = int(agglomerative), int(multi_traversal), cost_model
+    o.cost_dtype = C64 if cost_dtype == torch.complex64 else C128
     return o
+
+
+# --------------------------------------------------------------------- tuning
+TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "max_grid", "use_diag", "mfma_min_d",
+               "mfma_grid_per_cu", "mfma_direct_min_q")
+#: environment overrides (set for sweeps) take precedence over the tuning file
+_ENV_OF = {"direct_min_q": "CAST_DIRECT_MIN_Q", "tile_bits": "CAST_TILE_BITS", "direct_ipt": "CAST_DIRECT_IPT",
+           "direct_nt": "CAST_DIRECT_NT", "max_grid": "CAST_MAX_GRID", "use_diag": "CAST_USE_DIAG",
+           "mfma_min_d": "CAST_MFMA_MIN_D", "mfma_grid_per_cu": "CAST_MFMA_GRID_PER_CU",
+           "mfma_direct_min_q": "CAST_MFMA_DIRECT_MIN_Q"}
+TUNING_FILE = os.path.join(_HERE, "tuning_gfx950.json")
+
+
+def get_tuning(key, dtype=torch.complex128):
+    v = ctypes.c_int()
+    tuning_get(key.encode(), C128 if dtype == torch.complex128 else C64, ctypes.byref(v))
+    return v.value
+
+
+def set_tuning(key, value, dtype=torch.complex128):
+    tuning_set(key.encode(), C128 if dtype == torch.complex128 else C64, int(value))
+
+
+def apply_tuning_file(path=TUNING_FILE):
+    """Applies an autotuner result (see autotune.py): launch knobs and the
+    pass-cost table, skipping knobs overridden in the environment."""
+    import json
+    if not os.path.exists(path) or os.environ.get("CAST_NO_TUNING_FILE"):
+        return False
+    data = json.load(open(path))
+    for dname, dt in (("c64", C64), ("c128", C128)):
+        for key, value in data.get("knobs", {}).get(dname, {}).items():
+            env = _ENV_OF.get(key, "")
+            if os.environ.get(env) or os.environ.get(env + ("_C64" if dt == C64 else "_C128")):
+                continue
+            tuning_set(key.encode(), dt, int(value))
+        for entry in data.get("cost", {}).get(dname, []):
+            cost_table_set(dt, int(entry["k"]), int(entry["d"]), float(entry["ms_per_gamp"]))
+    return True
 
 
 class FusedCircuit:
@@ -400,3 +444,6 @@ class CircuitEnergy(torch.autograd.Function):
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
         return grad_out.to(g.device).unsqueeze(-1) * g, None, None, None, None
+
+
+apply_tuning_file()

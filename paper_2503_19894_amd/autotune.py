@@ -1,0 +1,143 @@
+"""Autotuner for libcast on the current GPU.
+
+Measures (1) the launch knobs of the pass kernels by coordinate descent on a
+representative suite of passes, and (2) the pass-cost table that the adaptive
+fusion check uses (one pass of a k-qubit gate whose nonzero pattern spans a
+d-dimensional XOR subspace), then writes both to tuning_gfx950.json next to
+the library, which the binding applies at import.
+
+    python paper_2503_19894_amd/autotune.py [--n 28] [--out PATH]
+
+The cost table follows the paper's CostModel idea (Sec. III-C): time gates of
+varied size and sparsity on the target and let fusion consult the table.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import paper_2503_19894_amd as cast  # noqa: E402
+from circuits import Gate, gate_sweep, haar_unitary, qft  # noqa: E402
+
+KNOB_CHOICES = [
+    ("direct_min_q", [3, 4, 5, 6]),
+    ("tile_bits", [11, 12, 13]),
+    ("direct_ipt", [1, 2, 4]),
+    ("direct_nt", [0, 1]),
+    ("mfma_direct_min_q", [0, 2, 4]),
+    ("mfma_grid_per_cu", [2, 4, 8]),
+    ("max_grid", [1 << 18, 1 << 20]),
+]
+
+
+def structured_unitary(k, d, rng):
+    """A k-qubit unitary whose nonzero pattern spans exactly the XOR subspace
+    of its first d qubits: (Haar on d qubits) x (random diagonal phases on
+    the other k - d), every block active."""
+    u = haar_unitary(1 << d, rng) if d else np.ones((1, 1), dtype=np.complex128)
+    ph = np.exp(1j * rng.uniform(0.1, 2 * math.pi - 0.1, 1 << (k - d)))
+    return np.kron(np.diag(ph), u)   # bit i < d: the Haar factor (least significant)
+
+
+def suite(n, dtype):
+    """Fused circuits whose passes cover every kernel class."""
+    rng = np.random.default_rng(0)
+    items = [cast.FusedCircuit(n, qft(n), k_max=5)]
+    for k, qs in ((4, (0, 1, 2, 3)), (5, (n - 5, n - 4, n - 3, n - 2, n - 1)), (6, (1, 7, 12, 18, 23, n - 1)),
+                  (3, (2, 9, 20)), (2, (0, 15))):
+        items.append(cast.FusedCircuit(n, [Gate("unitary", qs, matrix=haar_unitary(1 << k, rng))], k_max=k))
+    items.append(cast.FusedCircuit(n, gate_sweep("x", 3, (0, 1, 2)), k_max=3))
+    return items
+
+
+def time_suite(sv, items, reps=3):
+    best = []
+    for fc in items:
+        sv.apply_circuit(fc)
+        ts = [float(sv.apply_circuit_timed(fc).sum()) for _ in range(reps)]
+        best.append(min(ts))
+    return float(sum(best))
+
+
+def tune_knobs(n, dtype, log):
+    psi = torch.zeros(1 << n, dtype=dtype, device="cuda")
+    psi[0] = 1
+    sv = cast.StateVector(n, tensor=psi)
+    items = suite(n, dtype)
+    chosen = {}
+    base = time_suite(sv, items)
+    log(f"  start: {base:.2f} ms")
+    for key, values in KNOB_CHOICES:
+        cur = cast.get_tuning(key, dtype)
+        results = {}
+        for v in values:
+            cast.set_tuning(key, v, dtype)
+            results[v] = time_suite(sv, items)
+        best = min(results, key=results.get)
+        # keep the current value unless another is clearly better (> 1 %)
+        if results.get(cur, float("inf")) <= results[best] * 1.01:
+            best = cur
+        cast.set_tuning(key, best, dtype)
+        chosen[key] = best
+        log(f"  {key}: " + ", ".join(f"{v}: {t:.2f}" for v, t in results.items()) + f" -> {best}")
+    del sv, psi
+    torch.cuda.empty_cache()
+    return chosen
+
+
+def cost_table(n, dtype, log):
+    psi = torch.zeros(1 << n, dtype=dtype, device="cuda")
+    psi[0] = 1
+    sv = cast.StateVector(n, tensor=psi)
+    rng = np.random.default_rng(1)
+    spread = [0, 7, 13, 19, 23, n - 1]
+    out = []
+    for k in range(1, 7):
+        qs = tuple(spread[:k])
+        for d in range(0, k + 1):
+            fc = cast.FusedCircuit(n, [Gate("unitary", qs, matrix=structured_unitary(k, d, rng))], k_max=k)
+            assert fc.gate(0)["d"] == d
+            sv.apply_circuit(fc)
+            ms = min(float(sv.apply_circuit_timed(fc)[0]) for _ in range(3))
+            out.append({"k": k, "d": d, "ms_per_gamp": ms * 2.0 ** (30 - n)})
+        log(f"  k={k}: " + " ".join(f"d{e['d']}={e['ms_per_gamp']:.2f}" for e in out if e["k"] == k))
+    del sv, psi
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--out", default=os.path.join(HERE, "tuning_gfx950.json"))
+    args = ap.parse_args()
+    if not torch.cuda.is_available():
+        sys.exit("autotune needs a GPU")
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    result = {"device": torch.cuda.get_device_properties(0).gcnArchName, "n_qubits": args.n,
+              "knobs": {}, "cost": {}}
+    for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        log(f"{dname}: knobs")
+        result["knobs"][dname] = tune_knobs(args.n, dtype, log)
+        log(f"{dname}: cost table (ms per 2^30 amplitudes)")
+        result["cost"][dname] = cost_table(args.n, dtype, log)
+    result["seconds"] = round(time.time() - t0, 1)
+    with open(args.out, "w") as f:
+        json.dump(result, f, indent=1)
+    log(f"wrote {args.out} in {result['seconds']} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -47,6 +47,25 @@ Tuning &tuning() {
     return t;
 }
 
+// Pass-cost table (ms per 2^30 amplitudes), by dtype, k, d.  Initial values:
+// every pass streams the state once at 5 TB/s, plus the FMA time at half of
+// the FP peak for dense blocks.
+static double g_cost[3][kMaxK + 1][kMaxK + 1];
+static bool g_cost_init = [] {
+    for (int dt = 1; dt <= 2; ++dt)
+        for (int k = 1; k <= kMaxK; ++k)
+            for (int d = 0; d <= k; ++d) {
+                const double amp = dt == CAST_C128 ? 16.0 : 8.0;
+                const double mem_ms = 2.0 * amp * 1073741824.0 / 5e12 * 1e3;
+                const double peak = dt == CAST_C128 ? 78.6e12 : 157.3e12;
+                const double fl_ms = 8.0 * std::ldexp(1.0, d) * 1073741824.0 / (0.5 * peak) * 1e3;
+                g_cost[dt][k][d] = std::max(mem_ms, fl_ms);
+            }
+    return true;
+}();
+
+double pass_cost(cast_dtype dt, int k, int d) { return g_cost[dt][k][d]; }
+
 // ----------------------------------------------------------------- memory
 static std::mutex g_mem_mu;
 static size_t g_mem_used = 0;
@@ -345,6 +364,58 @@ cast_status gate_matrix(const char *name, const double *params, int *k, double *
     return CAST_OK;
 }
 
+static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi) {
+    Tuning &t = tuning();
+    const int i = dt == CAST_C64 ? CAST_C64 : CAST_C128;
+    *lo = 0;
+    *hi = 1 << 30;
+    if (key == "direct_min_q") { *hi = 34; return &t.direct_min_q[i]; }
+    if (key == "tile_bits") { *lo = 10; *hi = 13; return &t.tile_bits[i]; }
+    if (key == "direct_ipt") { *lo = 1; *hi = 4; return &t.direct_ipt; }
+    if (key == "direct_nt") { *hi = 1; return &t.direct_nt; }
+    if (key == "max_grid") { *lo = 256; return &t.max_grid; }
+    if (key == "use_diag") { *hi = 1; return &t.use_diag; }
+    if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
+    if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu; }
+    if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }
+    return nullptr;
+}
+
+cast_status tuning_set(const char *key, cast_dtype dt, int value) {
+    if (!key) return fail(CAST_EINVAL, "key is NULL");
+    int lo, hi;
+    int *f = tuning_field(key, dt, &lo, &hi);
+    if (!f) return fail(CAST_EINVAL, std::string("unknown tuning key ") + key);
+    if (value < lo || value > hi || (std::string(key) == "direct_ipt" && value == 3))
+        return fail(CAST_EINVAL, std::string("value out of range for ") + key);
+    *f = value;
+    return CAST_OK;
+}
+
+cast_status tuning_get(const char *key, cast_dtype dt, int *value) {
+    if (!key || !value) return fail(CAST_EINVAL, "NULL argument");
+    int lo, hi;
+    int *f = tuning_field(key, dt, &lo, &hi);
+    if (!f) return fail(CAST_EINVAL, std::string("unknown tuning key ") + key);
+    *value = *f;
+    return CAST_OK;
+}
+
+cast_status cost_table_set(cast_dtype dt, int k, int d, double v) {
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (k < 1 || k > kMaxK || d < 0 || d > k) return fail(CAST_EINVAL, "need 1 <= k <= 6, 0 <= d <= k");
+    if (!(v > 0)) return fail(CAST_EINVAL, "cost must be positive");
+    g_cost[dt][k][d] = v;
+    return CAST_OK;
+}
+
+cast_status cost_table_get(cast_dtype dt, int k, int d, double *v) {
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (k < 1 || k > kMaxK || d < 0 || d > k || !v) return fail(CAST_EINVAL, "bad argument");
+    *v = g_cost[dt][k][d];
+    return CAST_OK;
+}
+
 void fusion_opts_default(cast_fusion_opts *o) {
     if (!o) return;
     o->k_max = 5;
@@ -354,6 +425,7 @@ void fusion_opts_default(cast_fusion_opts *o) {
     o->agglomerative = 1;
     o->multi_traversal = 1;
     o->cost_model = 0;
+    o->cost_dtype = CAST_C128;
 }
 
 cast_status fuse_circuit(int n, const cast_gate *gates, size_t n_gates, const cast_fusion_opts *opts,
@@ -366,6 +438,9 @@ cast_status fuse_circuit(int n, const cast_gate *gates, size_t n_gates, const ca
     fusion_opts_default(&o);
     if (opts) o = *opts;
     if (o.k_max < 1 || o.k_max > kMaxK) return fail(CAST_EINVAL, "k_max must be in [1, 6]");
+    if (o.cost_model < 0 || o.cost_model > 1) return fail(CAST_EINVAL, "cost_model must be 0 or 1");
+    if (o.cost_dtype == 0) o.cost_dtype = CAST_C128;
+    if (o.cost_dtype != CAST_C64 && o.cost_dtype != CAST_C128) return fail(CAST_EINVAL, "bad cost_dtype");
     auto t0 = std::chrono::steady_clock::now();
     std::vector<FusionGate> in;
     in.reserve(n_gates);

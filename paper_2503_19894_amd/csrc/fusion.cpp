@@ -173,9 +173,18 @@ class Tile {
         for (int q : B.qubits)
             if (!std::binary_search(A.qubits.begin(), A.qubits.end(), q)) ++u;
         if (u > k) return false;
-        if (o_.opcount_cap > 0) {
+        if (o_.opcount_cap > 0 || o_.cost_model == 1) {
             Block f = product(A, B);
-            if (snapped_opcount(f.m) > o_.opcount_cap) return false;
+            if (o_.opcount_cap > 0 && snapped_opcount(f.m) > o_.opcount_cap) return false;
+            if (o_.cost_model == 1) {
+                // adaptive check (Sec. III-C): keep the fusion only if one pass of
+                // the product is predicted no slower than the two passes it replaces
+                const cast_dtype dt = (cast_dtype)o_.cost_dtype;
+                const double tf = pass_cost(dt, (int)f.qubits.size(), subspace_dim((int)f.qubits.size(), f.m, o_.zero_tol));
+                const double ta = pass_cost(dt, (int)A.qubits.size(), subspace_dim((int)A.qubits.size(), A.m, o_.zero_tol));
+                const double tb = pass_cost(dt, (int)B.qubits.size(), subspace_dim((int)B.qubits.size(), B.m, o_.zero_tol));
+                if (tf > ta + tb) return false;
+            }
         }
         return true;
     }

@@ -76,6 +76,10 @@ struct Tuning {                      // launch parameters chosen per (dtype, ker
     int max_grid = 1 << 20;
 };
 Tuning &tuning();
+// Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).
+double pass_cost(cast_dtype dt, int k, int d);
+// Dimension of the XOR subspace spanned by a matrix's nonzero pattern.
+int subspace_dim(int k, const std::vector<cplx> &m, double zero_tol);
 
 // Kernel a pass uses: 0 direct, 1 LDS tile, 2 LDS tile with two buffers,
 // 3 elementwise diagonal, 4 MFMA direct, 5 MFMA tile.

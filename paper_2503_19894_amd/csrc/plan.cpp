@@ -18,6 +18,32 @@ static double snap(double x, double zt, double ot) {
     return x;
 }
 
+int subspace_dim(int k, const std::vector<cplx> &m, double zt) {
+    const int D = 1 << k;
+    bool seen[64] = {false};
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) {
+            const cplx z = m[(size_t)r * D + c];
+            if (std::fabs(z.real()) > zt || std::fabs(z.imag()) > zt) seen[r ^ c] = true;
+        }
+    uint32_t basis[kMaxK];
+    int piv[kMaxK], d = 0;
+    for (uint32_t v0 = 1; v0 < (uint32_t)D; ++v0) {
+        if (!seen[v0]) continue;
+        uint32_t v = v0;
+        for (int i = 0; i < d; ++i)
+            if ((v >> piv[i]) & 1u) v ^= basis[i];
+        if (!v) continue;
+        const int pv = __builtin_ctz(v);
+        for (int i = 0; i < d; ++i)
+            if ((basis[i] >> pv) & 1u) basis[i] ^= v;
+        basis[d] = v;
+        piv[d] = pv;
+        ++d;
+    }
+    return d;
+}
+
 double opcount_of(const std::vector<cplx> &m) {
     double nnz = 0;
     for (const cplx &z : m) nnz += (z.real() != 0.0) + (z.imag() != 0.0);

@@ -139,3 +139,40 @@ def test_unsorted_qubits_and_permuted_matrix():
     for k in (2, 3, 5):
         fc = cast.FusedCircuit(n, gates, k_max=max(k, 3))
         np.testing.assert_allclose(replay(fc, n, psi0), oracle.run_circuit(n, gates, psi0), atol=1e-13, rtol=0)
+
+
+def test_adaptive_cost_model_reproduces_circuit_and_uses_table():
+    n = 8
+    gates = rqc_u3_cx(n, 4, seed=5)
+    psi0 = random_state(n, seed=6, workload=9)
+    want = oracle.run_circuit(n, gates, psi0)
+    fc = cast.FusedCircuit(n, gates, k_max=5, cost_model=1)
+    np.testing.assert_allclose(replay(fc, n, psi0), want, atol=1e-12, rtol=0)
+    # a table that makes dense 2-qubit passes prohibitively slow blocks every
+    # fusion that would produce one
+    import ctypes
+    old = ctypes.c_double()
+    cast.cost_table_get(cast.C128, 2, 2, ctypes.byref(old))
+    try:
+        cast.cost_table_set(cast.C128, 2, 2, 1e9)
+        fc2 = cast.FusedCircuit(n, gates, k_max=2, cost_model=1)
+        assert all(not (g["k"] == 2 and g["d"] == 2) for g in (fc2.gate(i) for i in range(len(fc2))))
+        np.testing.assert_allclose(replay(fc2, n, psi0), want, atol=1e-12, rtol=0)
+        fc3 = cast.FusedCircuit(n, gates, k_max=2, cost_model=0)
+        assert any(g["k"] == 2 and g["d"] == 2 for g in (fc3.gate(i) for i in range(len(fc3))))
+    finally:
+        cast.cost_table_set(cast.C128, 2, 2, old.value)
+
+
+def test_tuning_knobs_roundtrip_and_validation():
+    import torch
+    for key in cast.TUNING_KEYS:
+        v = cast.get_tuning(key, torch.complex64)
+        cast.set_tuning(key, v, torch.complex64)
+        assert cast.get_tuning(key, torch.complex64) == v
+    with pytest.raises(cast.CastError):
+        cast.set_tuning("no_such_knob", 1)
+    with pytest.raises(cast.CastError):
+        cast.set_tuning("direct_ipt", 3)
+    with pytest.raises(cast.CastError):
+        cast.cost_table_set(cast.C128, 7, 1, 1.0)
