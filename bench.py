@@ -151,6 +151,60 @@ def run_dense(n=32, depth=20, steps=1, warmup=1):
             "hbm_roof_s": sum(i["alg_bytes"] for i in infos) / 8e12}
 
 
+def run_tfim(ns=(16, 16, 20, 20, 24, 26), steps=50, dt=0.05, oracle_check=True):
+    """Mixed-size batch: Strang-Trotter evolution of transverse-field Ising
+    rings of different sizes from |+...+>, <Z_0> and its gradient w.r.t. every
+    field h_i, all instances in one batch (graph and persistent launch) vs the
+    plain per-instance adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import PauliTerm, tfim_fields, tfim_trotter
+
+    circs = [tfim_trotter(n, steps=steps, dt=dt) for n in ns]
+    fields = [tfim_fields(n, seed=i) for i, n in enumerate(ns)]
+    obs = [PauliTerm(1.0, ((0, "Z"),))]
+    out = {"n_qubits": list(ns), "trotter_steps": steps, "gates": [len(c) for c in circs]}
+    ref = None
+    for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        res = {}
+        for mname, mode in (("graph", cast.BATCH_STEPS_GRAPH), ("persistent", cast.BATCH_PERSISTENT_GRAPH)):
+            b = cast.Batch(circs, list(ns), list(ns), [obs] * len(ns), dtype=dtype, init=["plus"] * len(ns),
+                           mode=mode)
+            e, g = b.run(fields)        # warm-up (and the graph's first replay)
+            t0 = time.perf_counter()
+            e, g = b.run(fields)
+            res[mname] = {"s_per_batch": time.perf_counter() - t0, **b.info()}
+            del b
+            torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        pe, pg = [], []
+        for i, n in enumerate(ns):
+            init = cast.StateVector(n, tensor=torch.full((1 << n,), 2.0 ** (-n / 2), dtype=dtype, device="cuda"))
+            ei, gi = cast.adjoint(init, circs[i], fields[i], obs)
+            pe.append(ei)
+            pg.append(gi)
+        res["plain"] = {"s_per_batch": time.perf_counter() - t0}
+        best = min(res["graph"]["s_per_batch"], res["persistent"]["s_per_batch"])
+        res["batched_vs_plain"] = res["plain"]["s_per_batch"] / best
+        res["batched_plain_max_dgrad"] = float(max(np.max(np.abs(g[i] - pg[i])) for i in range(len(ns))))
+        res["z0"] = [float(x) for x in e]
+        if dname == "c128":
+            ref = (e, g)
+        else:
+            res["error_vs_fp64"] = {"z0": float(np.max(np.abs(e - ref[0]))),
+                                    "grad": float(max(np.max(np.abs(a - b)) for a, b in zip(g, ref[1])))}
+        out[dname] = res
+    if oracle_check:
+        import oracle
+        n = ns[0]
+        psi0 = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
+        ew, gw = oracle.adjoint_grad(n, circs[0], fields[0], obs, psi0)
+        out["oracle_n%d" % n] = {"z0_err": abs(ref[0][0] - ew), "grad_err": float(np.max(np.abs(ref[1][0] - gw)))}
+    return out
+
+
 def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_check=True):
     """Batched VQA gradients (hardware-efficient ansatz, H = sum Z_i Z_i+1 +
     0.5 sum X_i, parameter sets uniform in [-pi, pi]): grads/s of one batch
@@ -332,6 +386,8 @@ def main():
     ap.add_argument("--no-vqa", action="store_true")
     ap.add_argument("--vqa-only", action="store_true", help="only the batched VQA measurement")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-tfim", action="store_true")
+    ap.add_argument("--tfim-only", action="store_true", help="only the mixed-size TFIM batch")
     ap.add_argument("--dense-only", action="store_true", help="only the 32-qubit dense circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
@@ -353,6 +409,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.tfim_only:
+        print(json.dumps(run_tfim(oracle_check=False)), flush=True)
+        return
     if args.dense_only:
         print(json.dumps(run_dense()), flush=True)
         return
@@ -366,9 +425,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    progress("qft complex128")
     main_run = run_gpu(args.n, args.k_max, "c128", args.steps, args.warmup)
     extras = {}
     if not args.no_c64:
+        progress("qft complex64")
         extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup)
     dom = main_run["kernels"][main_run["dominant"]]
     traffic = recorded_traffic(main_run["dominant"])
@@ -376,8 +440,13 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"]}
+    progress("batched vqa")
     vqa = None if args.no_vqa else run_vqa(oracle_check=not args.no_cpu_baseline)
+    progress("dense 32-qubit circuit")
     dense = None if args.no_dense else run_dense()
+    progress("mixed-size tfim batch")
+    tfim = None if args.no_tfim else run_tfim(oracle_check=not args.no_cpu_baseline)
+    progress("cpu baseline (oracle)")
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
     line = {
         "metric": "effective HBM GB/s per fused-gate pass at 30q",
@@ -402,7 +471,7 @@ def main():
             "plain_c128": round(vqa["c128"]["plain"]["grads_per_s"], 2),
             "batched_c64": round(max(vqa["c64"]["graph"]["grads_per_s"], vqa["c64"]["persistent"]["grads_per_s"]), 2),
             "plain_c64": round(vqa["c64"]["plain"]["grads_per_s"], 2)},
-        "extras": {"c128": main_run, **extras, "vqa": vqa, "dense32": dense},
+        "extras": {"c128": main_run, **extras, "vqa": vqa, "dense32": dense, "tfim_mixed": tfim},
     }
     print(json.dumps(line), flush=True)
 

@@ -181,13 +181,14 @@ void fused_destroy(cast_fused *f);
 
 /* ------------------------------------------------------------ tuning */
 
-/* Launch knobs of the pass kernels, per dtype (dt = CAST_C64 or CAST_C128;
- * ignored for dtype-independent keys).  Keys: "direct_min_q" (smallest
+/* Launch knobs of the pass kernels, per dtype (dt = CAST_C64 or CAST_C128).  Keys: "direct_min_q" (smallest
  * target for the direct gather), "tile_bits" (log2 amplitudes per LDS tile),
  * "direct_ipt" (work items per thread: 1, 2 or 4), "direct_nt" (non-temporal
  * hints 0/1), "max_grid" (workgroup cap), "use_diag" (elementwise diagonal
  * kernel 0/1), "mfma_min_d" (smallest block dimension for the matrix cores,
- * 4..7; 7 disables them), "mfma_grid_per_cu", "mfma_direct_min_q".
+ * 4..7; 7 disables them), "mfma_grid_per_cu", "mfma_direct_min_q",
+ * "diag_unroll" (diagonal kernel chunks per thread: 1, 2, 4, 8),
+ * "diag_max_grid", "diag_lds_table" (phases in LDS 1 / read from L1 0).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

@@ -35,6 +35,9 @@ KNOB_CHOICES = [
     ("mfma_direct_min_q", [0, 2, 4]),
     ("mfma_grid_per_cu", [2, 4, 8]),
     ("max_grid", [1 << 18, 1 << 20]),
+    ("diag_unroll", [2, 4, 8]),
+    ("diag_max_grid", [1 << 14, 1 << 16, 1 << 18, 1 << 20]),
+    ("diag_lds_table", [0, 1]),
 ]
 
 

@@ -25,23 +25,25 @@ cast_status fail(cast_status code, const std::string &msg) {
 Tuning &tuning() {
     static Tuning t = [] {
         Tuning x;
-        // environment overrides for sweeps: CAST_DIRECT_MIN_Q_C64/C128, CAST_TILE_BITS_C64/C128
-        auto env = [](const char *name, int &v) {
-            if (const char *s = std::getenv(name)) v = std::atoi(s);
+        // CAST_<KNOB> sets both dtypes, CAST_<KNOB>_C64 / _C128 one of them
+        auto env = [](const char *name, int *v) {
+            if (const char *s = std::getenv(name)) v[CAST_C64] = v[CAST_C128] = std::atoi(s);
+            const std::string n64 = std::string(name) + "_C64", n128 = std::string(name) + "_C128";
+            if (const char *s = std::getenv(n64.c_str())) v[CAST_C64] = std::atoi(s);
+            if (const char *s = std::getenv(n128.c_str())) v[CAST_C128] = std::atoi(s);
         };
-        env("CAST_DIRECT_MIN_Q_C64", x.direct_min_q[CAST_C64]);
-        env("CAST_DIRECT_MIN_Q_C128", x.direct_min_q[CAST_C128]);
-        env("CAST_TILE_BITS_C64", x.tile_bits[CAST_C64]);
-        env("CAST_TILE_BITS_C128", x.tile_bits[CAST_C128]);
-        env("CAST_MAX_GRID", x.max_grid);
+        env("CAST_DIRECT_MIN_Q", x.direct_min_q);
+        env("CAST_TILE_BITS", x.tile_bits);
         env("CAST_DIRECT_IPT", x.direct_ipt);
         env("CAST_DIRECT_NT", x.direct_nt);
+        env("CAST_MAX_GRID", x.max_grid);
         env("CAST_USE_DIAG", x.use_diag);
-        env("CAST_MFMA_MIN_D_C64", x.mfma_min_d[CAST_C64]);
-        env("CAST_MFMA_MIN_D_C128", x.mfma_min_d[CAST_C128]);
+        env("CAST_DIAG_UNROLL", x.diag_unroll);
+        env("CAST_DIAG_MAX_GRID", x.diag_max_grid);
+        env("CAST_DIAG_LDS_TABLE", x.diag_lds_table);
+        env("CAST_MFMA_MIN_D", x.mfma_min_d);
         env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
-        env("CAST_MFMA_DIRECT_MIN_Q_C64", x.mfma_direct_min_q[CAST_C64]);
-        env("CAST_MFMA_DIRECT_MIN_Q_C128", x.mfma_direct_min_q[CAST_C128]);
+        env("CAST_MFMA_DIRECT_MIN_Q", x.mfma_direct_min_q);
         return x;
     }();
     return t;
@@ -371,12 +373,15 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     *hi = 1 << 30;
     if (key == "direct_min_q") { *hi = 34; return &t.direct_min_q[i]; }
     if (key == "tile_bits") { *lo = 10; *hi = 13; return &t.tile_bits[i]; }
-    if (key == "direct_ipt") { *lo = 1; *hi = 4; return &t.direct_ipt; }
-    if (key == "direct_nt") { *hi = 1; return &t.direct_nt; }
-    if (key == "max_grid") { *lo = 256; return &t.max_grid; }
-    if (key == "use_diag") { *hi = 1; return &t.use_diag; }
+    if (key == "direct_ipt") { *lo = 1; *hi = 4; return &t.direct_ipt[i]; }
+    if (key == "direct_nt") { *hi = 1; return &t.direct_nt[i]; }
+    if (key == "max_grid") { *lo = 256; return &t.max_grid[i]; }
+    if (key == "use_diag") { *hi = 1; return &t.use_diag[i]; }
+    if (key == "diag_unroll") { *lo = 1; *hi = 8; return &t.diag_unroll[i]; }
+    if (key == "diag_max_grid") { *lo = 256; return &t.diag_max_grid[i]; }
+    if (key == "diag_lds_table") { *hi = 1; return &t.diag_lds_table[i]; }
     if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
-    if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu; }
+    if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu[i]; }
     if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }
     return nullptr;
 }
@@ -386,7 +391,8 @@ cast_status tuning_set(const char *key, cast_dtype dt, int value) {
     int lo, hi;
     int *f = tuning_field(key, dt, &lo, &hi);
     if (!f) return fail(CAST_EINVAL, std::string("unknown tuning key ") + key);
-    if (value < lo || value > hi || (std::string(key) == "direct_ipt" && value == 3))
+    if (value < lo || value > hi || (std::string(key) == "direct_ipt" && value == 3) ||
+        (std::string(key) == "diag_unroll" && (value & (value - 1))))
         return fail(CAST_EINVAL, std::string("value out of range for ") + key);
     *f = value;
     return CAST_OK;

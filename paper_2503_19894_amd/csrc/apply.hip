@@ -166,70 +166,95 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
 // whatever the targets are, so every access is coalesced; a lane whose
 // amplitudes all have D[j] = 1 issues neither the load nor the store, and
 // whole cache lines of such amplitudes never leave HBM.
-template <typename R, int U>
+template <typename R, int U, bool LDS_TABLE>
 __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__restrict__ table, DiagArgs a) {
     using V = typename Amp<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;   // log2(amplitudes per 16-byte chunk)
-    __shared__ V tab[64];
-    const int D = 1 << a.k;
-    for (int j = threadIdx.x; j < D; j += 256) {
-        V t;
-        t.x = table[2 * j];
-        t.y = table[2 * j + 1];
-        tab[j] = t;
+    constexpr int A = 1 << S;
+    // phases: staged in LDS, or read straight from the (L1-resident) table
+    __shared__ V tab_lds[LDS_TABLE ? 64 : 1];
+    const V *tab = LDS_TABLE ? tab_lds : reinterpret_cast<const V *>(table);
+    if (LDS_TABLE) {
+        const int D = 1 << a.k;
+        for (int j = threadIdx.x; j < D; j += 256) {
+            V t;
+            t.x = table[2 * j];
+            t.y = table[2 * j + 1];
+            tab_lds[j] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     native_u4 *p16 = reinterpret_cast<native_u4 *>(psi_r);
+    // j(x) = bits of amplitude x at the targets.  In the main loop a chunk's
+    // amplitude index is (uniform iteration base) + (threadIdx.x << S) + h with
+    // the base a multiple of 256 << S, so j splits into a per-lane part
+    // (computed once) and a wave-uniform part (one scalar pass per iteration).
     auto jof = [&](uint64_t x) {
         uint32_t j = 0;
         for (int i = 0; i < a.k; ++i) j |= (uint32_t)((x >> a.q[i]) & 1u) << i;
         return j;
     };
-    auto update = [&](native_u4 &w, uint64_t c) {
+    uint32_t jl[A];
+#pragma unroll
+    for (int h = 0; h < A; ++h) jl[h] = jof(((uint64_t)threadIdx.x << S) | (uint64_t)h);
+    constexpr uint64_t per = 256ull * U;
+    const uint64_t nfull = a.nchunks / per;
+    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
+        native_u4 w[U];
+        uint32_t ju[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t c0 = it * per + (uint64_t)u * 256;       // uniform
+            ju[u] = jof(c0 << S);
+            const uint64_t c = c0 + threadIdx.x;
+            bool any = false;
+#pragma unroll
+            for (int h = 0; h < A; ++h) any |= (a.amask >> (ju[u] | jl[h])) & 1u;
+            act[u] = any;
+            if (any) w[u] = __builtin_nontemporal_load(p16 + c);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!act[u]) continue;
+            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
+            V *v = reinterpret_cast<V *>(&w[u]);
+#pragma unroll
+            for (int h = 0; h < A; ++h) {
+                const uint32_t j = ju[u] | jl[h];
+                if ((a.amask >> j) & 1u) {
+                    const V t = tab[j];
+                    const R re = v[h].x * t.x - v[h].y * t.y;
+                    const R im = v[h].x * t.y + v[h].y * t.x;
+                    v[h].x = re;
+                    v[h].y = im;
+                }
+            }
+            __builtin_nontemporal_store(w[u], p16 + c);
+        }
+    }
+    for (uint64_t c = nfull * per + (uint64_t)blockIdx.x * 256 + threadIdx.x; c < a.nchunks;
+         c += (uint64_t)gridDim.x * 256) {
+        bool any = false;
+        uint32_t js[A];
+#pragma unroll
+        for (int h = 0; h < A; ++h) {
+            js[h] = jof((c << S) | (uint64_t)h);
+            any |= (a.amask >> js[h]) & 1u;
+        }
+        if (!any) continue;
+        native_u4 w = p16[c];
         V *v = reinterpret_cast<V *>(&w);
 #pragma unroll
-        for (int h = 0; h < (1 << S); ++h) {
-            const uint32_t j = jof((c << S) | (uint64_t)h);
-            if ((a.amask >> j) & 1u) {
-                const V t = tab[j];
+        for (int h = 0; h < A; ++h) {
+            if ((a.amask >> js[h]) & 1u) {
+                const V t = tab[js[h]];
                 const R re = v[h].x * t.x - v[h].y * t.y;
                 const R im = v[h].x * t.y + v[h].y * t.x;
                 v[h].x = re;
                 v[h].y = im;
             }
         }
-    };
-    auto active = [&](uint64_t c) {
-        bool any = false;
-#pragma unroll
-        for (int h = 0; h < (1 << S); ++h) any |= (a.amask >> jof((c << S) | (uint64_t)h)) & 1u;
-        return any;
-    };
-    constexpr uint64_t per = 256ull * U;
-    const uint64_t nfull = a.nchunks / per;
-    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
-        native_u4 w[U];
-        bool act[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
-            act[u] = active(c);
-            if (act[u]) w[u] = __builtin_nontemporal_load(p16 + c);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
-            if (act[u]) {
-                update(w[u], c);
-                __builtin_nontemporal_store(w[u], p16 + c);
-            }
-        }
-    }
-    for (uint64_t c = nfull * per + (uint64_t)blockIdx.x * 256 + threadIdx.x; c < a.nchunks;
-         c += (uint64_t)gridDim.x * 256) {
-        if (!active(c)) continue;
-        native_u4 w = p16[c];
-        update(w, c);
         p16[c] = w;
     }
 }
@@ -583,7 +608,7 @@ static void launch_direct_t(int D, R *psi, const R *m, const PassArgs &a, int gr
 // block already needs many registers.
 static int direct_ipt(int D, cast_dtype dt) {
     const int amps_cap = dt == CAST_C128 ? 8 : 16;   // amplitudes a lane holds across its items
-    int ipt = tuning().direct_ipt;
+    int ipt = tuning().direct_ipt[dt];
     while (ipt > 1 && (ipt * (1 << D) > amps_cap || D > 3)) ipt >>= 1;
     return ipt;
 }
@@ -591,10 +616,10 @@ static int direct_ipt(int D, cast_dtype dt) {
 template <typename R>
 static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const PassArgs &a, hipStream_t s) {
     const int ipt = direct_ipt(D, dt);
-    const bool nt = tuning().direct_nt != 0;
+    const bool nt = tuning().direct_nt[dt] != 0;
     const uint64_t items = a.ngroups * a.nblk;
     uint64_t grid = (items + 256ull * ipt - 1) / (256ull * ipt);
-    if (grid > (uint64_t)tuning().max_grid) grid = tuning().max_grid;
+    if (grid > (uint64_t)tuning().max_grid[dt]) grid = tuning().max_grid[dt];
     if (grid < 1) grid = 1;
     const int g = (int)grid;
     switch (ipt * 2 + (nt ? 1 : 0)) {
@@ -643,13 +668,28 @@ static hipError_t launch_tile(int D, bool uni, bool twobuf, R *psi, const R *m, 
     return hipGetLastError();
 }
 
+template <typename R>
+static hipError_t launch_diag(int U, bool lds_table, R *psi, const R *m, const DiagArgs &g, int grid, hipStream_t s) {
+#define CAST_DIAG(UU)                                                                                     \
+    case UU:                                                                                              \
+        if (lds_table) hipLaunchKernelGGL((k_diag<R, UU, true>), dim3(grid), dim3(256), 0, s, psi, m, g);  \
+        else hipLaunchKernelGGL((k_diag<R, UU, false>), dim3(grid), dim3(256), 0, s, psi, m, g);          \
+        break;
+    switch (U) {
+        CAST_DIAG(1) CAST_DIAG(2) CAST_DIAG(4) CAST_DIAG(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef CAST_DIAG
+    return hipGetLastError();
+}
+
 // Registers hold 2^d input amplitudes per lane; beyond this the kernel
 // re-reads inputs from LDS (TWOBUF).
 static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 5; }
 
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p) {
     const Tuning &tu = tuning();
-    if (p.d == 0 && tu.use_diag) return 3;
+    if (p.d == 0 && tu.use_diag[dt]) return 3;
     if (p.d >= tu.mfma_min_d[dt] && mfma_fits(n, dt, p)) {
         if (p.q[0] >= tu.mfma_direct_min_q[dt] && (n - p.k) >= 4) return 4;
         return 5;
@@ -740,7 +780,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         if (kind == 4) {
             const uint64_t units = (a.ngroups >> 4) * a.nblk;
             grid = (units + 3) / 4;
-            const uint64_t cap = (uint64_t)tu.mfma_grid_per_cu * 256;
+            const uint64_t cap = (uint64_t)tu.mfma_grid_per_cu[dt] * 256;
             if (grid > cap) grid = cap;
         } else {
             const int tb = mfma_tile_bits(n, dt, p);
@@ -768,7 +808,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             }
             a.ntiles = 1ull << (n - tb);
             grid = a.ntiles;
-            if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
+            if (grid > (uint64_t)tu.max_grid[dt]) grid = tu.max_grid[dt];
             lds += ((size_t)1 << tb) * amp_bytes(dt);
         }
         if (dt == CAST_C128)
@@ -783,16 +823,11 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         for (uint32_t b : p.blk) g.amask |= 1ull << b;
         g.nchunks = ((uint64_t)1 << n) * amp_bytes(dt) / 16;
         if (g.nchunks == 0) g.nchunks = 1;   // c64, n = 1: one chunk holds both amplitudes
-        constexpr int U = 4;
-        uint64_t grid = (g.nchunks + 256 * U - 1) / (256 * U);
-        if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
-        if (dt == CAST_C128)
-            hipLaunchKernelGGL((k_diag<double, U>), dim3((int)grid), dim3(256), 0, stream, (double *)psi,
-                               (const double *)dmat, g);
-        else
-            hipLaunchKernelGGL((k_diag<float, U>), dim3((int)grid), dim3(256), 0, stream, (float *)psi,
-                               (const float *)dmat, g);
-        e = hipGetLastError();
+        const int U = tu.diag_unroll[dt];
+        uint64_t grid = (g.nchunks + 256ull * U - 1) / (256ull * U);
+        if (grid > (uint64_t)tu.diag_max_grid[dt]) grid = tu.diag_max_grid[dt];
+        if (dt == CAST_C128) e = launch_diag<double>(U, tu.diag_lds_table[dt] != 0, (double *)psi, (const double *)dmat, g, (int)grid, stream);
+        else e = launch_diag<float>(U, tu.diag_lds_table[dt] != 0, (float *)psi, (const float *)dmat, g, (int)grid, stream);
     } else if (direct) {
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
         a.log_ngroups = n - k;
@@ -832,7 +867,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         a.ntiles = 1ull << (n - tb);
         const int wg = 256;
         uint64_t grid = a.ntiles;
-        if (grid > (uint64_t)tu.max_grid) grid = tu.max_grid;
+        if (grid > (uint64_t)tu.max_grid[dt]) grid = tu.max_grid[dt];
         const bool uni = (tb - k) >= 6;
         const size_t lds = ((size_t)1 << tb) * amp_bytes(dt) * (twobuf ? 2 : 1);
         if (dt == CAST_C128)

@@ -33,6 +33,8 @@ struct InstPlan {
     std::vector<uint64_t> gx, gz;          // global generator masks per gate
     std::vector<int> gslot;                // result slot per gate (-1: none)
     std::vector<HostOp> ops;
+    int tb = 0;                            // tile bits of this instance's segments
+    std::vector<std::vector<int>> seg_gates;   // per op (FWD/ADJ): gates in processing order
     std::vector<uint64_t> mat_fwd, mat_adj;  // matrix offsets (complex entries) per gate
     size_t nparams = 0;
     int nslots = 0;
@@ -50,6 +52,8 @@ struct cast_batch {
     // device
     void *states = nullptr;
     cast::BatchRec *d_recs = nullptr;
+    cast::SegGate *d_segs = nullptr;
+    size_t lds_bytes = 0;
     uint64_t *d_step_rec = nullptr, *d_step_item = nullptr;
     cast::BatchInst *d_insts = nullptr;
     void *d_mats = nullptr;
@@ -145,11 +149,11 @@ static cast_status queue_program(cast_batch *b) {
     if (b->mode == 2) {
         if (cast_status rc = batch_zero(b->d_counters, 2 + (size_t)b->ninst, s)) return rc;
         if (cast_status rc = batch_launch_persistent(b->dev, b->dt, b->total_items, b->persistent_grid,
-                                                     b->d_counters, 1u << 24, b->persistent_chunk, s))
+                                                     b->d_counters, 1u << 24, b->persistent_chunk, b->lds_bytes, s))
             return rc;
     } else {
         for (int st = 0; st < b->nsteps; ++st)
-            if (cast_status rc = batch_launch_step(b->dev, b->dt, st, b->step_items[st], s)) return rc;
+            if (cast_status rc = batch_launch_step(b->dev, b->dt, st, b->step_items[st], b->lds_bytes, s)) return rc;
     }
     if (cast_status rc = batch_finish(b->dev, s)) return rc;
     CAST_HIP_TRY(hipMemcpyAsync(b->h_results, b->d_results, b->result_doubles * sizeof(double),
@@ -167,6 +171,7 @@ static void free_batch(cast_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     dev_free(b->states);
     dev_free(b->d_recs);
+    dev_free(b->d_segs);
     dev_free(b->d_step_rec);
     dev_free(b->d_step_item);
     dev_free(b->d_insts);
@@ -216,11 +221,13 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     std::vector<BatchInst> hinst(n_inst);
     size_t state_elems = 0;
     // amplitudes per work item, and the cache budget of an instance group
-    int item_log2 = 13;
+    // tile of a segment: 2^11 complex128 or 2^12 complex64 amplitudes, psi
+    // and lambda together 64 KiB of LDS
+    int tile_bits = dt == CAST_C128 ? 11 : 12;
+    if (const char *e = std::getenv("CAST_BATCH_TILE_BITS")) tile_bits = std::min(12, std::max(4, atoi(e)));
     // per-step launches: groups sized for the 256 MB last-level cache; the
     // persistent launch keeps every instance in one step-major stream
     double group_bytes = mode == 2 ? 0.0 : 192.0 * (1 << 20);
-    if (const char *e = std::getenv("CAST_BATCH_ITEM_LOG2")) item_log2 = std::max(8, atoi(e));
     if (const char *e = std::getenv("CAST_BATCH_GROUP_MB"))
         if (mode != 2) group_bytes = atof(e) * (1 << 20);
     uint64_t mat_entries = 0, part = 0, res = 0;
@@ -285,10 +292,39 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
             mat_entries += (uint64_t)D * D;
         }
         ip.nslots = slot;
-        for (size_t l = 0; l < L; ++l) ip.ops.push_back(HostOp{BK_FWD, (int)l, -1});
+        // segments: consecutive gates (forward order, then reverse order)
+        // whose qubits together fit one tile of 2^tb amplitudes
+        ip.tb = std::min(n, tile_bits);
+        auto segment = [&](bool reverse) {
+            std::vector<std::vector<int>> segs;
+            std::vector<int> cur;
+            uint64_t qm = 0;
+            for (size_t c = 0; c < L; ++c) {
+                const int l = reverse ? (int)(L - 1 - c) : (int)c;
+                uint64_t gm = 0;
+                for (int a = 0; a < ip.gates[l].k; ++a) gm |= 1ull << ip.gates[l].qubits[a];
+                if (!cur.empty() && __builtin_popcountll(qm | gm) > ip.tb) {
+                    segs.push_back(cur);
+                    cur.clear();
+                    qm = 0;
+                }
+                cur.push_back(l);
+                qm |= gm;
+            }
+            if (!cur.empty()) segs.push_back(cur);
+            return segs;
+        };
+        for (auto &sg : segment(false)) {
+            ip.ops.push_back(HostOp{BK_FWD, -1, -1});
+            ip.seg_gates.push_back(sg);
+        }
         ip.ops.push_back(HostOp{BK_HPSI, -1, 0});
-        for (size_t l = L; l-- > 0;) ip.ops.push_back(HostOp{BK_ADJ, (int)l, ip.gslot[l]});
-        ip.wgs = n > item_log2 ? (1u << (n - item_log2)) : 1u;
+        ip.seg_gates.emplace_back();
+        for (auto &sg : segment(true)) {
+            ip.ops.push_back(HostOp{BK_ADJ, -1, -1});
+            ip.seg_gates.push_back(sg);
+        }
+        ip.wgs = 1u << (n - ip.tb);
         // Hamiltonian, grouped by x mask
         if (n_terms[i] && !hams[i]) return bail(fail(CAST_EINVAL, "Hamiltonian is NULL"));
         BatchInst &bi = hinst[i];
@@ -364,6 +400,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         }
     }
     std::vector<BatchRec> recs;
+    std::vector<SegGate> segs;
     uint64_t item_base = 0;
     for (auto &gr : groups) {
     size_t max_ops = 0;
@@ -384,15 +421,43 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
             r.wgs = ip.wgs;
             r.slot = op.slot;
             r.need = (uint64_t)s * ip.wgs;
+            r.tb = ip.tb;
             if (op.kind != BK_HPSI) {
-                const int l = op.gate;
-                r.k = ip.gates[l].k;
-                r.q0 = ip.sq0[l];
-                r.q1 = ip.sq1[l];
-                r.xl = ip.xl[l];
-                r.zl = ip.zl[l];
-                r.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
-                if (op.kind == BK_ADJ && ip.gslot[l] < 0) r.slot = -1;
+                // tile geometry: smallest khi with #{segment qubits >= tb - khi} == khi
+                const std::vector<int> &gl = ip.seg_gates[s];
+                uint64_t qm = 0;
+                for (int l : gl)
+                    for (int a = 0; a < ip.gates[l].k; ++a) qm |= 1ull << ip.gates[l].qubits[a];
+                int khi = 0;
+                for (;; ++khi) {
+                    const int lim = ip.tb - khi;
+                    const uint64_t above = lim >= 64 ? 0 : (qm & ~((1ull << lim) - 1));
+                    if (__builtin_popcountll(above) == khi) break;
+                }
+                r.khi = khi;
+                r.W = ip.tb - khi;
+                int pos[64];
+                int h = 0;
+                for (int q = 0; q < ip.n; ++q) {
+                    if (!((qm >> q) & 1ull)) continue;
+                    if (q < r.W) pos[q] = q;
+                    else { r.qhi[h] = (uint8_t)q; pos[q] = r.W + h; ++h; }
+                }
+                r.sg0 = (uint32_t)segs.size();
+                for (int l : gl) {
+                    SegGate sgt;
+                    memset(&sgt, 0, sizeof sgt);
+                    sgt.k = ip.gates[l].k;
+                    sgt.t0 = pos[ip.sq0[l]];
+                    sgt.t1 = sgt.k == 2 ? pos[ip.sq1[l]] : -1;
+                    sgt.slot = op.kind == BK_ADJ ? ip.gslot[l] : -1;
+                    sgt.xl = ip.xl[l];
+                    sgt.zl = ip.zl[l];
+                    sgt.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
+                    segs.push_back(sgt);
+                }
+                r.sg1 = (uint32_t)segs.size();
+                r.slot = -1;
             }
             recs.push_back(r);
             items += ip.wgs;
@@ -418,6 +483,12 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         off += 2 * N;
     }
     if (cast_status rc = upload(&b->d_recs, recs)) return bail(rc);
+    if (cast_status rc = upload(&b->d_segs, segs)) return bail(rc);
+    {
+        int tbm = 0;
+        for (auto &ip : b->inst) tbm = std::max(tbm, ip.tb);
+        b->lds_bytes = 2 * ((size_t)1 << tbm) * amp_bytes(dt);
+    }
     if (cast_status rc = upload(&b->d_step_rec, b->step_rec)) return bail(rc);
     if (cast_status rc = upload(&b->d_step_item, b->step_item)) return bail(rc);
     if (cast_status rc = upload(&b->d_insts, hinst)) return bail(rc);
@@ -443,6 +514,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         return bail(fail(CAST_EHIP, "hipStreamCreate failed"));
     BatchDev &d = b->dev;
     d.recs = b->d_recs;
+    d.segs = b->d_segs;
     d.step_rec = b->d_step_rec;
     d.step_item = b->d_step_item;
     d.insts = b->d_insts;

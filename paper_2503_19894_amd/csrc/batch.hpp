@@ -3,12 +3,16 @@
 //
 // Each instance's program is a list of ops, op s of every instance forming
 // global step s:
-//   FWD  psi <- U psi                                   (one op per gate)
+//   FWD  a segment of consecutive gates applied to psi
 //   HPSI lambda <- H psi, partial sums of <psi|lambda>  (energy)
-//   ADJ  partial sums of <lambda|G|psi>, then psi <- U^dag psi, lambda <- U^dag lambda
-// Every op of an instance is split into `wgs` equal work items (one
-// workgroup each); partial sums of item w land in a fixed slot, and a final
-// kernel adds them in a fixed order.
+//   ADJ  a segment of gates in reverse order: for each, partial sums of
+//        <lambda|G|psi>, then psi <- U^dag psi, lambda <- U^dag lambda
+// A segment holds consecutive gates whose qubits together fit one LDS tile
+// (the low window [0, W) plus the segment's qubits at or above W): a work
+// item loads one tile of psi (and lambda), applies every gate of the segment
+// in LDS in order, and writes the tile back, so one HBM pass serves many
+// gates.  Every op of an instance has `wgs` items (tiles); partial sums of
+// item w land in a fixed slot, and a final kernel adds them in a fixed order.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,15 +25,23 @@ namespace cast {
 
 enum BatchKind : uint32_t { BK_FWD = 0, BK_HPSI = 1, BK_ADJ = 2 };
 
+struct SegGate {            // one gate of a segment, in tile coordinates
+    int k;
+    int t0, t1;             // tile bits of the sorted targets (t1 unused for k = 1)
+    int slot;               // ADJ: result slot, or -1
+    uint32_t xl, zl;        // ADJ: generator x/z masks in local (group) index bits
+    uint64_t mat;           // offset (complex entries) of U (FWD) or U^dag (ADJ)
+};
+
 struct BatchRec {           // op `s` of one instance
     uint32_t kind;
     uint32_t inst;
     uint32_t item0;         // first item of this record within its step
     uint32_t wgs;           // items (workgroups) of this record
-    int k, q0, q1;          // sorted targets (k <= 2)
-    int slot;               // result slot, or -1
-    uint32_t xl, zl;        // ADJ: generator x/z masks in local (group) index bits
-    uint64_t mat;           // offset (complex entries) of the op's 2^k x 2^k matrix
+    int slot;               // HPSI result slot
+    uint32_t sg0, sg1;      // FWD/ADJ: gates [sg0, sg1) of the SegGate table
+    int tb, W, khi;         // tile: 2^tb amplitudes, window [0, W), khi high qubits
+    uint8_t qhi[12];        // high qubits of the tile, ascending
     uint64_t need;          // persistent mode: items of this instance that must be done first
 };
 
@@ -51,6 +63,7 @@ struct BatchInst {
 
 struct BatchDev {           // device pointers of one program
     const BatchRec *recs;   // all records, step-major
+    const SegGate *segs;
     const uint64_t *step_rec;    // nsteps + 1: first record of each step
     const uint64_t *step_item;   // nsteps + 1: first global item of each step (persistent mode)
     const BatchInst *insts;
@@ -64,13 +77,14 @@ struct BatchDev {           // device pointers of one program
 };
 
 // Queues step s (one launch over all its records).
-cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, hipStream_t st);
+cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, size_t lds,
+                              hipStream_t st);
 // Queues the whole program as one persistent launch: workgroups pull items
 // in global order from a counter; an item waits until its instance has
 // finished the previous op.  Waits are bounded by spin_limit polls; on
 // overrun *err becomes nonzero and every workgroup exits.
 cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
-                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk,
+                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk, size_t lds,
                                     hipStream_t st);
 // Zeroes `n` 64-bit counters with a kernel (graph-capture safe).
 cast_status batch_zero(unsigned long long *p, size_t n, hipStream_t st);

@@ -12,6 +12,8 @@
 
 namespace cast {
 
+extern __shared__ uint4 batch_lds[];
+
 template <typename R> struct BAmp;
 template <> struct BAmp<double> { using T = double2; };
 template <> struct BAmp<float> { using T = float2; };
@@ -56,60 +58,103 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
-// FWD / ADJ over groups [g0, g1) of a K-qubit gate.
+// One gate of a segment applied to the LDS tile(s); ADJ gates with a slot
+// first accumulate sum_j conj(lam[j ^ x]) (-1)^{|z & j|} psi[j] over their
+// groups (the generator acts inside each group).
 template <int K, typename R>
-__device__ void gate_range(const BatchRec &rec, const BatchInst &in, const R *mats, uint64_t g0, uint64_t g1,
-                           double *pre, double *pim) {
+__device__ void seg_gate(const SegGate &G, bool adj, int tb, const R *m, typename BAmp<R>::T *tp,
+                         typename BAmp<R>::T *tl, double *sre, double *sim) {
     using V = typename BAmp<R>::T;
     constexpr int D = 1 << K;
-    V *psi = reinterpret_cast<V *>(in.psi);
-    V *lam = reinterpret_cast<V *>(in.lam);
-    const R *m = mats + 2 * rec.mat;
-    uint64_t off[D];
+    const uint32_t ngroups = 1u << (tb - K);
+    uint32_t off[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        uint64_t o = 0;
-        if (j & 1) o |= 1ull << rec.q0;
-        if (K == 2 && (j & 2)) o |= 1ull << rec.q1;
-        off[j] = o;
-    }
-    double sre = 0.0, sim = 0.0;
-    for (uint64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-        uint64_t base = ins0(g, rec.q0);
-        if (K == 2) base = ins0(base, rec.q1);
+    for (int j = 0; j < D; ++j) off[j] = ((j & 1) ? (1u << G.t0) : 0u) | ((K == 2 && (j & 2)) ? (1u << G.t1) : 0u);
+    for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+        uint32_t base = (uint32_t)ins0(g, G.t0);
+        if (K == 2) base = (uint32_t)ins0(base, G.t1);
         V x[D], y[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = psi[base | off[j]];
-        if (rec.kind == BK_FWD) {
+        for (int j = 0; j < D; ++j) x[j] = tp[base | off[j]];
+        if (!adj) {
             small_matvec<K>(m, x, y);
 #pragma unroll
-            for (int j = 0; j < D; ++j) psi[base | off[j]] = y[j];
-        } else {
-            V l[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) l[j] = lam[base | off[j]];
-            if (rec.slot >= 0) {
-                // sum_j conj(lam[j ^ x]) (-1)^{|z & j|} psi[j]: the generator acts inside the group
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const V a = l[j ^ rec.xl];
-                    const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
-                    const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
-                    const bool neg = __popc(rec.zl & (uint32_t)j) & 1;
-                    sre += neg ? -pr : pr;
-                    sim += neg ? -pi : pi;
-                }
-            }
-            small_matvec<K>(m, x, y);
-#pragma unroll
-            for (int j = 0; j < D; ++j) psi[base | off[j]] = y[j];
-            small_matvec<K>(m, l, y);
-#pragma unroll
-            for (int j = 0; j < D; ++j) lam[base | off[j]] = y[j];
+            for (int j = 0; j < D; ++j) tp[base | off[j]] = y[j];
+            continue;
         }
+        V l[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) l[j] = tl[base | off[j]];
+        if (G.slot >= 0) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const V a = l[j ^ G.xl];
+                const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
+                const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
+                const bool neg = __popc(G.zl & (uint32_t)j) & 1;
+                *sre += neg ? -pr : pr;
+                *sim += neg ? -pi : pi;
+            }
+        }
+        small_matvec<K>(m, x, y);
+#pragma unroll
+        for (int j = 0; j < D; ++j) tp[base | off[j]] = y[j];
+        small_matvec<K>(m, l, y);
+#pragma unroll
+        for (int j = 0; j < D; ++j) tl[base | off[j]] = y[j];
     }
-    *pre = sre;
-    *pim = sim;
+}
+
+// Global amplitude index of tile element e (window bits, then the high
+// qubits in order) for tile t of record rec.
+__device__ __forceinline__ uint64_t seg_addr(const BatchRec &rec, uint64_t tbase, uint32_t e) {
+    const uint32_t r = e >> rec.W;
+    uint64_t x = tbase | (e & ((1u << rec.W) - 1));
+    for (int j = 0; j < rec.khi; ++j)
+        if ((r >> j) & 1u) x |= 1ull << rec.qhi[j];
+    return x;
+}
+
+// FWD / ADJ segment on tile w of an instance.
+template <typename R>
+__device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst &in, uint32_t w, double *red,
+                         typename BAmp<R>::T *lds) {
+    using V = typename BAmp<R>::T;
+    const bool adj = rec.kind == BK_ADJ;
+    const uint32_t T = 1u << rec.tb;
+    V *tp = lds, *tl = lds + T;
+    V *psi = reinterpret_cast<V *>(in.psi);
+    V *lam = reinterpret_cast<V *>(in.lam);
+    uint64_t tbase = (uint64_t)w << rec.W;
+    for (int j = 0; j < rec.khi; ++j) tbase = ins0(tbase, rec.qhi[j]);
+    for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
+        const uint64_t x = seg_addr(rec, tbase, e);
+        tp[e] = psi[x];
+        if (adj) tl[e] = lam[x];
+    }
+    __syncthreads();
+    const R *mats = reinterpret_cast<const R *>(d.mats);
+    for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) {
+        const SegGate G = d.segs[sg];
+        double re = 0.0, im = 0.0;
+        if (G.k == 1) seg_gate<1, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
+        else seg_gate<2, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
+        if (adj && G.slot >= 0) {
+            const double sre = block_sum(re, red);
+            const double sim = block_sum(im, red);
+            if (threadIdx.x == 0) {
+                double *p = d.partials + in.part_off + 2 * ((uint64_t)G.slot * in.wgs + w);
+                p[0] = sre;
+                p[1] = sim;
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
+        const uint64_t x = seg_addr(rec, tbase, e);
+        psi[x] = tp[e];
+        if (adj) lam[x] = tl[e];
+    }
 }
 
 // lambda[y] = (H psi)[y] for y in [y0, y1), and partial <psi|lambda>.
@@ -153,16 +198,16 @@ __device__ void hpsi_range(const BatchInst &in, const PauliSumGroup *tg, const P
 // One work item: item w of record rec.
 template <typename R>
 __device__ void run_item(const BatchDev &d, const BatchRec &rec, uint32_t w, double *red) {
+    using V = typename BAmp<R>::T;
     const BatchInst in = d.insts[rec.inst];
-    const R *mats = reinterpret_cast<const R *>(d.mats);
+    if (rec.kind != BK_HPSI) {
+        seg_item<R>(d, rec, in, w, red, reinterpret_cast<V *>(batch_lds));
+        return;
+    }
     double re = 0.0, im = 0.0;
-    if (rec.kind == BK_HPSI) {
+    {
         const uint64_t N = 1ull << in.n, per = N / rec.wgs;
         hpsi_range<R>(in, d.tg, d.tt, per * w, per * (w + 1), &re, &im);
-    } else {
-        const uint64_t G = 1ull << (in.n - rec.k), per = G / rec.wgs;
-        if (rec.k == 1) gate_range<1, R>(rec, in, mats, per * w, per * (w + 1), &re, &im);
-        else gate_range<2, R>(rec, in, mats, per * w, per * (w + 1), &re, &im);
     }
     if (rec.slot >= 0) {
         const double sre = block_sum(re, red);
@@ -234,13 +279,15 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
                     __hip_atomic_fetch_add(&counters[2 + pend_inst], pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     pend = 0;
                 }
-                if (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
+                // poll with relaxed loads (an acquire per poll would invalidate the
+                // caches under every other workgroup), then acquire once
+                if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
                     if (pend) {
                         __hip_atomic_fetch_add(done, pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         pend = 0;
                     }
                     uint32_t spins = 0;
-                    while (__hip_atomic_load(done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
+                    while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
                         if (++spins > spin_limit ||
                             __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             atomicExch(&counters[1], 1ull);
@@ -250,6 +297,7 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
                         __builtin_amdgcn_s_sleep(2);
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
             if (stop_sh) break;
@@ -315,20 +363,21 @@ static cast_status launched(const char *what) {
     return CAST_OK;
 }
 
-cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, hipStream_t st) {
-    if (dt == CAST_C128) hipLaunchKernelGGL(k_batch_step<double>, dim3((uint32_t)nitems), dim3(256), 0, st, d, s);
-    else hipLaunchKernelGGL(k_batch_step<float>, dim3((uint32_t)nitems), dim3(256), 0, st, d, s);
+cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, size_t lds,
+                              hipStream_t st) {
+    if (dt == CAST_C128) hipLaunchKernelGGL(k_batch_step<double>, dim3((uint32_t)nitems), dim3(256), lds, st, d, s);
+    else hipLaunchKernelGGL(k_batch_step<float>, dim3((uint32_t)nitems), dim3(256), lds, st, d, s);
     return launched("batched step launch");
 }
 
 cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
-                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk,
+                                    unsigned long long *counters, uint32_t spin_limit, uint32_t chunk, size_t lds,
                                     hipStream_t st) {
     if (dt == CAST_C128)
-        hipLaunchKernelGGL(k_batch_persistent<double>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
+        hipLaunchKernelGGL(k_batch_persistent<double>, dim3(grid), dim3(256), lds, st, d, total_items, counters,
                            spin_limit, chunk);
     else
-        hipLaunchKernelGGL(k_batch_persistent<float>, dim3(grid), dim3(256), 0, st, d, total_items, counters,
+        hipLaunchKernelGGL(k_batch_persistent<float>, dim3(grid), dim3(256), lds, st, d, total_items, counters,
                            spin_limit, chunk);
     return launched("persistent batch launch");
 }

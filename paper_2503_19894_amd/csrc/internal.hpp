@@ -64,16 +64,19 @@ struct DeviceMatrix {                // a plan's block matrices in the state dty
     size_t bytes = 0;
 };
 
-struct Tuning {                      // launch parameters chosen per (dtype, kernel)
-    int direct_min_q[3] = {0, 4, 4}; // smallest target for the direct kernel, by dtype
-    int tile_bits[3] = {0, 12, 12};  // LDS tile size log2(amplitudes), by dtype
-    int direct_ipt = 4;              // work items per thread per iteration (capped by registers)
-    int direct_nt = 1;               // non-temporal loads/stores in the direct kernel
-    int use_diag = 1;                // elementwise kernel for diagonal passes
-    int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels, by dtype
-    int mfma_grid_per_cu = 4;        // MFMA direct kernel: workgroups per CU
-    int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather, by dtype
-    int max_grid = 1 << 20;
+struct Tuning {                      // launch parameters, by dtype index (CAST_C64, CAST_C128)
+    int direct_min_q[3] = {0, 4, 4}; // smallest target for the direct kernel
+    int tile_bits[3] = {0, 12, 12};  // LDS tile size log2(amplitudes)
+    int direct_ipt[3] = {0, 4, 4};   // work items per thread per iteration (capped by registers)
+    int direct_nt[3] = {0, 1, 1};    // non-temporal loads/stores in the direct kernel
+    int max_grid[3] = {0, 1 << 20, 1 << 20};
+    int use_diag[3] = {0, 1, 1};     // elementwise kernel for diagonal passes
+    int diag_unroll[3] = {0, 4, 4};  // diagonal kernel: 16-byte chunks per thread per iteration
+    int diag_max_grid[3] = {0, 1 << 20, 1 << 20};
+    int diag_lds_table[3] = {0, 1, 1};   // diagonal kernel: phases staged in LDS (else read from L1)
+    int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels
+    int mfma_grid_per_cu[3] = {0, 4, 4};
+    int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).
