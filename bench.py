@@ -33,19 +33,30 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_label(info, dtype_name):
-    kind = info["kernel"]
+    """Name of the kernel template instance a pass launches, as the profiler
+    prints it (without the argument list), from the library's active knobs."""
+    import torch
+
+    import paper_2503_19894_amd as cast
+
+    dt = torch.complex128 if dtype_name == "c128" else torch.complex64
+    kind, d = info["kernel"], info["d"]
     r = "double" if dtype_name == "c128" else "float"
     if kind == 3:
-        return f"k_diag<{r}, 4>"
-    if kind == 4:
-        return f"k_mfma_direct<{info['d']}, {r}>"
-    if kind == 5:
-        return f"k_mfma_tile<{info['d']}, {r}>"
+        lds = "true" if cast.get_tuning("diag_lds_table", dt) else "false"
+        return f"k_diag<{r}, {cast.get_tuning('diag_unroll', dt)}, {lds}>"
     if kind == 0:
-        return f"k_direct<{info['d']}, {r}>"
-    uni = "true"  # tiles hold >= 64 groups at n = 30
+        ipt, cap = cast.get_tuning("direct_ipt", dt), 8 if dtype_name == "c128" else 16
+        while ipt > 1 and (ipt * (1 << d) > cap or d > 3):
+            ipt >>= 1
+        nt = "true" if cast.get_tuning("direct_nt", dt) else "false"
+        return f"k_direct<{d}, {r}, {ipt}, {nt}>"
+    if kind == 4:
+        return f"k_mfma_direct<{d}, {r}>"
+    if kind == 5:
+        return f"k_mfma_tile<{d}, {r}>"
     two = "true" if kind == 2 else "false"
-    return f"k_tile<{info['d']}, {r}, {uni}, {two}>"
+    return f"k_tile<{d}, {r}, true, {two}>"
 
 
 def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):

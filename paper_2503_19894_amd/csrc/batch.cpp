@@ -303,7 +303,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 const int l = reverse ? (int)(L - 1 - c) : (int)c;
                 uint64_t gm = 0;
                 for (int a = 0; a < ip.gates[l].k; ++a) gm |= 1ull << ip.gates[l].qubits[a];
-                if (!cur.empty() && __builtin_popcountll(qm | gm) > ip.tb) {
+                if (!cur.empty() && (__builtin_popcountll(qm | gm) > ip.tb || cur.size() >= (size_t)kSegMaxGates)) {
                     segs.push_back(cur);
                     cur.clear();
                     qm = 0;
@@ -487,7 +487,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     {
         int tbm = 0;
         for (auto &ip : b->inst) tbm = std::max(tbm, ip.tb);
-        b->lds_bytes = 2 * ((size_t)1 << tbm) * amp_bytes(dt);
+        b->lds_bytes = 2 * ((size_t)1 << tbm) * amp_bytes(dt) + kSegLdsExtra;
     }
     if (cast_status rc = upload(&b->d_step_rec, b->step_rec)) return bail(rc);
     if (cast_status rc = upload(&b->d_step_item, b->step_item)) return bail(rc);

@@ -25,6 +25,10 @@ namespace cast {
 
 enum BatchKind : uint32_t { BK_FWD = 0, BK_HPSI = 1, BK_ADJ = 2 };
 
+constexpr int kSegMaxGates = 64;   // gates per segment (bounds the LDS reduction area)
+// LDS of a segment item beyond its two tiles: address tables + partial sums
+constexpr size_t kSegLdsExtra = 128 * sizeof(uint64_t) + (size_t)kSegMaxGates * 4 * 2 * sizeof(double);
+
 struct SegGate {            // one gate of a segment, in tile coordinates
     int k;
     int t0, t1;             // tile bits of the sorted targets (t1 unused for k = 1)

@@ -105,56 +105,117 @@ __device__ void seg_gate(const SegGate &G, bool adj, int tb, const R *m, typenam
     }
 }
 
-// Global amplitude index of tile element e (window bits, then the high
-// qubits in order) for tile t of record rec.
-__device__ __forceinline__ uint64_t seg_addr(const BatchRec &rec, uint64_t tbase, uint32_t e) {
-    const uint32_t r = e >> rec.W;
-    uint64_t x = tbase | (e & ((1u << rec.W) - 1));
-    for (int j = 0; j < rec.khi; ++j)
-        if ((r >> j) & 1u) x |= 1ull << rec.qhi[j];
-    return x;
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-// FWD / ADJ segment on tile w of an instance.
+// FWD / ADJ segment on tile w of an instance.  LDS layout: psi tile, lambda
+// tile (2^tb amplitudes each), two 64-entry tables that deposit the 12 bits
+// of a run index onto the tile's high qubits, and per-gate, per-wave partial
+// sums of the segment's inner products (at most kSegMaxGates gates).
 template <typename R>
 __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst &in, uint32_t w, double *red,
                          typename BAmp<R>::T *lds) {
     using V = typename BAmp<R>::T;
+    constexpr int S = sizeof(V) == 16 ? 0 : 1;      // log2(amplitudes per 16-byte chunk)
     const bool adj = rec.kind == BK_ADJ;
     const uint32_t T = 1u << rec.tb;
     V *tp = lds, *tl = lds + T;
+    uint64_t *hid = reinterpret_cast<uint64_t *>(lds + 2 * T);   // [2][64]
+    double *gsum = reinterpret_cast<double *>(hid + 128);         // [kSegMaxGates][4 waves][2]
     V *psi = reinterpret_cast<V *>(in.psi);
     V *lam = reinterpret_cast<V *>(in.lam);
     uint64_t tbase = (uint64_t)w << rec.W;
     for (int j = 0; j < rec.khi; ++j) tbase = ins0(tbase, rec.qhi[j]);
-    for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
-        const uint64_t x = seg_addr(rec, tbase, e);
-        tp[e] = psi[x];
-        if (adj) tl[e] = lam[x];
+    if (threadIdx.x < 128) {
+        const uint32_t h = threadIdx.x >> 6, r = threadIdx.x & 63;
+        uint64_t x = 0;
+        for (int j = 0; j < 6; ++j) {
+            const int bit = 6 * (int)h + j;
+            if (bit < rec.khi && ((r >> j) & 1u)) x |= 1ull << rec.qhi[bit];
+        }
+        hid[threadIdx.x] = x;
+    }
+    __syncthreads();
+    // 16-byte chunks of the tile (a run holds at least one chunk when W >= S)
+    const bool chunked = rec.W >= S;
+    const uint32_t nchunk = chunked ? (T >> S) : T;
+    const uint32_t wmask = (1u << rec.W) - 1;
+    auto addr = [&](uint32_t e) {
+        const uint32_t r = e >> rec.W;
+        return tbase | (e & wmask) | hid[r & 63] | hid[64 + (r >> 6)];
+    };
+    if (chunked) {
+        uint4 *t16p = reinterpret_cast<uint4 *>(tp), *t16l = reinterpret_cast<uint4 *>(tl);
+        const uint4 *p16 = reinterpret_cast<const uint4 *>(psi), *l16 = reinterpret_cast<const uint4 *>(lam);
+        for (uint32_t c = threadIdx.x; c < nchunk; c += blockDim.x) {
+            const uint64_t x = addr(c << S) >> S;
+            t16p[c] = p16[x];
+            if (adj) t16l[c] = l16[x];
+        }
+    } else {
+        for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
+            const uint64_t x = addr(e);
+            tp[e] = psi[x];
+            if (adj) tl[e] = lam[x];
+        }
     }
     __syncthreads();
     const R *mats = reinterpret_cast<const R *>(d.mats);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int nred = 0;
     for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) {
         const SegGate G = d.segs[sg];
         double re = 0.0, im = 0.0;
         if (G.k == 1) seg_gate<1, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
         else seg_gate<2, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
         if (adj && G.slot >= 0) {
-            const double sre = block_sum(re, red);
-            const double sim = block_sum(im, red);
-            if (threadIdx.x == 0) {
-                double *p = d.partials + in.part_off + 2 * ((uint64_t)G.slot * in.wgs + w);
-                p[0] = sre;
-                p[1] = sim;
+            re = wave_sum64(re);
+            im = wave_sum64(im);
+            if (lane == 0) {
+                gsum[(nred * 4 + wave) * 2] = re;
+                gsum[(nred * 4 + wave) * 2 + 1] = im;
             }
+            ++nred;
         }
         __syncthreads();
     }
-    for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
-        const uint64_t x = seg_addr(rec, tbase, e);
-        psi[x] = tp[e];
-        if (adj) lam[x] = tl[e];
+    // one partial per inner product: its four waves in a fixed order
+    if (adj && nred) {
+        int idx = 0;
+        for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) {
+            const int slot = d.segs[sg].slot;
+            if (slot < 0) continue;
+            if ((int)threadIdx.x == (idx & 255)) {
+                double sre = 0.0, sim = 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    sre += gsum[(idx * 4 + v) * 2];
+                    sim += gsum[(idx * 4 + v) * 2 + 1];
+                }
+                double *p = d.partials + in.part_off + 2 * ((uint64_t)slot * in.wgs + w);
+                p[0] = sre;
+                p[1] = sim;
+            }
+            ++idx;
+        }
     }
+    if (chunked) {
+        const uint4 *t16p = reinterpret_cast<const uint4 *>(tp), *t16l = reinterpret_cast<const uint4 *>(tl);
+        uint4 *p16 = reinterpret_cast<uint4 *>(psi), *l16 = reinterpret_cast<uint4 *>(lam);
+        for (uint32_t c = threadIdx.x; c < nchunk; c += blockDim.x) {
+            const uint64_t x = addr(c << S) >> S;
+            p16[x] = t16p[c];
+            if (adj) l16[x] = t16l[c];
+        }
+    } else {
+        for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
+            const uint64_t x = addr(e);
+            psi[x] = tp[e];
+            if (adj) lam[x] = tl[e];
+        }
+    }
+    __syncthreads();   // the LDS tables and tiles are reused by the next item
 }
 
 // lambda[y] = (H psi)[y] for y in [y0, y1), and partial <psi|lambda>.
@@ -363,8 +424,25 @@ static cast_status launched(const char *what) {
     return CAST_OK;
 }
 
+// Raises the kernels' dynamic-LDS limit once (segment items use more than 64 KiB).
+template <typename R>
+static hipError_t allow_lds() {
+    static hipError_t done = [] {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch_step<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           128 << 10);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_batch_persistent<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    128 << 10);
+        return e;
+    }();
+    return done;
+}
+
 cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t nitems, size_t lds,
                               hipStream_t st) {
+    if (lds > (128u << 10)) return fail(CAST_EUNSUPPORTED, "segment tiles exceed 128 KiB of LDS");
+    const hipError_t ae = dt == CAST_C128 ? allow_lds<double>() : allow_lds<float>();
+    if (ae != hipSuccess) return fail(CAST_EHIP, std::string("LDS attribute: ") + hipGetErrorString(ae));
     if (dt == CAST_C128) hipLaunchKernelGGL(k_batch_step<double>, dim3((uint32_t)nitems), dim3(256), lds, st, d, s);
     else hipLaunchKernelGGL(k_batch_step<float>, dim3((uint32_t)nitems), dim3(256), lds, st, d, s);
     return launched("batched step launch");
@@ -373,6 +451,9 @@ cast_status batch_launch_step(const BatchDev &d, cast_dtype dt, int s, uint64_t 
 cast_status batch_launch_persistent(const BatchDev &d, cast_dtype dt, uint64_t total_items, int grid,
                                     unsigned long long *counters, uint32_t spin_limit, uint32_t chunk, size_t lds,
                                     hipStream_t st) {
+    if (lds > (128u << 10)) return fail(CAST_EUNSUPPORTED, "segment tiles exceed 128 KiB of LDS");
+    const hipError_t ae = dt == CAST_C128 ? allow_lds<double>() : allow_lds<float>();
+    if (ae != hipSuccess) return fail(CAST_EHIP, std::string("LDS attribute: ") + hipGetErrorString(ae));
     if (dt == CAST_C128)
         hipLaunchKernelGGL(k_batch_persistent<double>, dim3(grid), dim3(256), lds, st, d, total_items, counters,
                            spin_limit, chunk);
