@@ -234,7 +234,7 @@ cast_status adjoint_grad(const cast_sv *init, const cast_gate *gates, size_t n_g
 /* Many parametrised circuits evaluated together on one GPU: the same
  * structure with different parameter sets (variational algorithms run the
  * same circuit thousands of times), or circuits of different qubit counts.
- * Each instance i has n_qubits[i] qubits (2..34), its own gate list
+ * Each instance i has n_qubits[i] qubits (3..34), its own gate list
  * (1- and 2-qubit gates; parametrised gates as in cast_gate), n_params[i]
  * parameters and Pauli sum H_i, and starts from init_kind[i]:
  * CAST_INIT_ZERO |0...0>, CAST_INIT_PLUS |+...+>, or CAST_INIT_STATE a copy

@@ -53,6 +53,7 @@ struct cast_batch {
     void *states = nullptr;
     cast::BatchRec *d_recs = nullptr;
     cast::SegGate *d_segs = nullptr;
+    cast::SegSweep *d_sweeps = nullptr;
     size_t lds_bytes = 0;
     uint64_t *d_step_rec = nullptr, *d_step_item = nullptr;
     cast::BatchInst *d_insts = nullptr;
@@ -172,6 +173,7 @@ static void free_batch(cast_batch *b) {
     dev_free(b->states);
     dev_free(b->d_recs);
     dev_free(b->d_segs);
+    dev_free(b->d_sweeps);
     dev_free(b->d_step_rec);
     dev_free(b->d_step_item);
     dev_free(b->d_insts);
@@ -238,7 +240,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     for (int i = 0; i < n_inst; ++i) {
         InstPlan &ip = b->inst[i];
         const int n = n_qubits[i];
-        if (n < 2 || n > kMaxQubits) return bail(fail(CAST_EINVAL, "instance qubit count must be in [2, 34]"));
+        if (n < 3 || n > kMaxQubits) return bail(fail(CAST_EINVAL, "instance qubit count must be in [3, 34]"));
         if (n_gates[i] && !circuits[i]) return bail(fail(CAST_EINVAL, "circuit is NULL"));
         ip.n = n;
         ip.nparams = n_params[i];
@@ -401,6 +403,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     }
     std::vector<BatchRec> recs;
     std::vector<SegGate> segs;
+    std::vector<SegSweep> sweeps;
     uint64_t item_base = 0;
     for (auto &gr : groups) {
     size_t max_ops = 0;
@@ -443,20 +446,54 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                     if (q < r.W) pos[q] = q;
                     else { r.qhi[h] = (uint8_t)q; pos[q] = r.W + h; ++h; }
                 }
+                // sweeps: consecutive gates on at most three tile bits (padded
+                // with the lowest other tile bits to exactly three)
                 r.sg0 = (uint32_t)segs.size();
-                for (int l : gl) {
-                    SegGate sgt;
-                    memset(&sgt, 0, sizeof sgt);
-                    sgt.k = ip.gates[l].k;
-                    sgt.t0 = pos[ip.sq0[l]];
-                    sgt.t1 = sgt.k == 2 ? pos[ip.sq1[l]] : -1;
-                    sgt.slot = op.kind == BK_ADJ ? ip.gslot[l] : -1;
-                    sgt.xl = ip.xl[l];
-                    sgt.zl = ip.zl[l];
-                    sgt.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
-                    segs.push_back(sgt);
+                r.sw0 = (uint32_t)sweeps.size();
+                int nparam = 0;
+                size_t gi = 0;
+                while (gi < gl.size()) {
+                    uint32_t bits = 0;
+                    size_t gj = gi;
+                    for (; gj < gl.size(); ++gj) {
+                        const int l = gl[gj];
+                        uint32_t gb = 1u << pos[ip.sq0[l]];
+                        if (ip.gates[l].k == 2) gb |= 1u << pos[ip.sq1[l]];
+                        if (__builtin_popcount(bits | gb) > 3) break;
+                        bits |= gb;
+                    }
+                    for (int t = 0; __builtin_popcount(bits) < 3 && t < ip.tb; ++t) bits |= 1u << t;
+                    SegSweep sw;
+                    memset(&sw, 0, sizeof sw);
+                    int loc[32];
+                    for (int t = 0, c = 0; t < ip.tb; ++t)
+                        if ((bits >> t) & 1u) sw.b[c] = t, loc[t] = c++;
+                    sw.g0 = (uint32_t)segs.size();
+                    sw.p0 = nparam;
+                    for (size_t q = gi; q < gj; ++q) {
+                        const int l = gl[q];
+                        SegGate sgt;
+                        memset(&sgt, 0, sizeof sgt);
+                        sgt.k = ip.gates[l].k;
+                        sgt.t0 = loc[pos[ip.sq0[l]]];
+                        sgt.t1 = sgt.k == 2 ? loc[pos[ip.sq1[l]]] : -1;
+                        sgt.slot = op.kind == BK_ADJ ? ip.gslot[l] : -1;
+                        // generator masks: gate-local bit 0 / 1 -> sweep bits t0 / t1
+                        for (int bb = 0; bb < sgt.k; ++bb) {
+                            const int sb = bb == 0 ? sgt.t0 : sgt.t1;
+                            if ((ip.xl[l] >> bb) & 1u) sgt.xl |= 1u << sb;
+                            if ((ip.zl[l] >> bb) & 1u) sgt.zl |= 1u << sb;
+                        }
+                        sgt.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
+                        if (sgt.slot >= 0) ++nparam;
+                        segs.push_back(sgt);
+                    }
+                    sw.g1 = (uint32_t)segs.size();
+                    sweeps.push_back(sw);
+                    gi = gj;
                 }
                 r.sg1 = (uint32_t)segs.size();
+                r.sw1 = (uint32_t)sweeps.size();
                 r.slot = -1;
             }
             recs.push_back(r);
@@ -484,6 +521,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     }
     if (cast_status rc = upload(&b->d_recs, recs)) return bail(rc);
     if (cast_status rc = upload(&b->d_segs, segs)) return bail(rc);
+    if (cast_status rc = upload(&b->d_sweeps, sweeps)) return bail(rc);
     {
         int tbm = 0;
         for (auto &ip : b->inst) tbm = std::max(tbm, ip.tb);
@@ -515,6 +553,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     BatchDev &d = b->dev;
     d.recs = b->d_recs;
     d.segs = b->d_segs;
+    d.sweeps = b->d_sweeps;
     d.step_rec = b->d_step_rec;
     d.step_item = b->d_step_item;
     d.insts = b->d_insts;

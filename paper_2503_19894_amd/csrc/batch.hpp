@@ -29,12 +29,18 @@ constexpr int kSegMaxGates = 64;   // gates per segment (bounds the LDS reductio
 // LDS of a segment item beyond its two tiles: address tables + partial sums
 constexpr size_t kSegLdsExtra = 128 * sizeof(uint64_t) + (size_t)kSegMaxGates * 4 * 2 * sizeof(double);
 
-struct SegGate {            // one gate of a segment, in tile coordinates
+struct SegGate {            // one gate of a sweep, in sweep coordinates
     int k;
-    int t0, t1;             // tile bits of the sorted targets (t1 unused for k = 1)
+    int t0, t1;             // sweep bits (0..2) of the sorted targets (t1 unused for k = 1)
     int slot;               // ADJ: result slot, or -1
-    uint32_t xl, zl;        // ADJ: generator x/z masks in local (group) index bits
+    uint32_t xl, zl;        // ADJ: generator x/z masks over the sweep bits
     uint64_t mat;           // offset (complex entries) of U (FWD) or U^dag (ADJ)
+};
+
+struct SegSweep {           // consecutive gates of a segment on at most three tile bits
+    int b[3];               // the sweep's tile bits, ascending
+    uint32_t g0, g1;        // its gates [g0, g1) of the SegGate table
+    int p0;                 // index of its first inner product within the segment
 };
 
 struct BatchRec {           // op `s` of one instance
@@ -44,6 +50,7 @@ struct BatchRec {           // op `s` of one instance
     uint32_t wgs;           // items (workgroups) of this record
     int slot;               // HPSI result slot
     uint32_t sg0, sg1;      // FWD/ADJ: gates [sg0, sg1) of the SegGate table
+    uint32_t sw0, sw1;      // FWD/ADJ: sweeps [sw0, sw1) of the SegSweep table
     int tb, W, khi;         // tile: 2^tb amplitudes, window [0, W), khi high qubits
     uint8_t qhi[12];        // high qubits of the tile, ascending
     uint64_t need;          // persistent mode: items of this instance that must be done first
@@ -68,6 +75,7 @@ struct BatchInst {
 struct BatchDev {           // device pointers of one program
     const BatchRec *recs;   // all records, step-major
     const SegGate *segs;
+    const SegSweep *sweeps;
     const uint64_t *step_rec;    // nsteps + 1: first record of each step
     const uint64_t *step_item;   // nsteps + 1: first global item of each step (persistent mode)
     const BatchInst *insts;

@@ -58,50 +58,83 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
-// One gate of a segment applied to the LDS tile(s); ADJ gates with a slot
-// first accumulate sum_j conj(lam[j ^ x]) (-1)^{|z & j|} psi[j] over their
-// groups (the generator acts inside each group).
-template <int K, typename R>
-__device__ void seg_gate(const SegGate &G, bool adj, int tb, const R *m, typename BAmp<R>::T *tp,
-                         typename BAmp<R>::T *tl, double *sre, double *sim) {
-    using V = typename BAmp<R>::T;
-    constexpr int D = 1 << K;
-    const uint32_t ngroups = 1u << (tb - K);
-    uint32_t off[D];
+// Gates on a thread's 8 register amplitudes x[j], j over the sweep's three
+// tile bits.  Bit positions are template parameters so every register index
+// is a compile-time constant.
+template <int B, typename V, typename R>
+__device__ __forceinline__ void reg_apply1(V *x, const R *m) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) off[j] = ((j & 1) ? (1u << G.t0) : 0u) | ((K == 2 && (j & 2)) ? (1u << G.t1) : 0u);
-    for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
-        uint32_t base = (uint32_t)ins0(g, G.t0);
-        if (K == 2) base = (uint32_t)ins0(base, G.t1);
-        V x[D], y[D];
+    for (int j = 0; j < 8; ++j) {
+        if (j & (1 << B)) continue;
+        const int j1 = j | (1 << B);
+        const V a = x[j], b = x[j1];
+        V y0, y1;
+        y0.x = y0.y = y1.x = y1.y = 0;
+        y0 = cmul_acc(y0, m[0], m[1], a);
+        y0 = cmul_acc(y0, m[2], m[3], b);
+        y1 = cmul_acc(y1, m[4], m[5], a);
+        y1 = cmul_acc(y1, m[6], m[7], b);
+        x[j] = y0;
+        x[j1] = y1;
+    }
+}
+
+template <int B0, int B1, typename V, typename R>
+__device__ __forceinline__ void reg_apply2(V *x, const R *m) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = tp[base | off[j]];
-        if (!adj) {
-            small_matvec<K>(m, x, y);
+    for (int j = 0; j < 8; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int idx[4] = {j, j | (1 << B0), j | (1 << B1), j | (1 << B0) | (1 << B1)};
+        V in[4], out[4];
 #pragma unroll
-            for (int j = 0; j < D; ++j) tp[base | off[j]] = y[j];
-            continue;
+        for (int c = 0; c < 4; ++c) in[c] = x[idx[c]];
+        small_matvec<2>(m, in, out);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[idx[r]] = out[r];
+    }
+}
+
+template <typename V, typename R>
+__device__ __forceinline__ void reg_apply(const SegGate &G, V *x, const R *m) {
+    if (G.k == 1) {
+        switch (G.t0) {
+            case 0: reg_apply1<0>(x, m); break;
+            case 1: reg_apply1<1>(x, m); break;
+            default: reg_apply1<2>(x, m); break;
         }
-        V l[D];
+    } else if (G.t0 == 0) {
+        if (G.t1 == 1) reg_apply2<0, 1>(x, m);
+        else reg_apply2<0, 2>(x, m);
+    } else {
+        reg_apply2<1, 2>(x, m);
+    }
+}
+
+// sum_j conj(l[j ^ X]) (-1)^{|z & j|} x[j] over the 8 register amplitudes
+template <int X, typename V>
+__device__ __forceinline__ void reg_inner_x(const V *l, const V *x, uint32_t zl, double *re, double *im) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) l[j] = tl[base | off[j]];
-        if (G.slot >= 0) {
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const V a = l[j ^ G.xl];
-                const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
-                const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
-                const bool neg = __popc(G.zl & (uint32_t)j) & 1;
-                *sre += neg ? -pr : pr;
-                *sim += neg ? -pi : pi;
-            }
-        }
-        small_matvec<K>(m, x, y);
-#pragma unroll
-        for (int j = 0; j < D; ++j) tp[base | off[j]] = y[j];
-        small_matvec<K>(m, l, y);
-#pragma unroll
-        for (int j = 0; j < D; ++j) tl[base | off[j]] = y[j];
+    for (int j = 0; j < 8; ++j) {
+        const V a = l[j ^ X];
+        const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
+        const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
+        const bool neg = __popc(zl & (uint32_t)j) & 1;
+        *re += neg ? -pr : pr;
+        *im += neg ? -pi : pi;
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ void reg_inner(const V *l, const V *x, uint32_t xl, uint32_t zl, double *re, double *im) {
+    switch (xl) {
+        case 0: reg_inner_x<0>(l, x, zl, re, im); break;
+        case 1: reg_inner_x<1>(l, x, zl, re, im); break;
+        case 2: reg_inner_x<2>(l, x, zl, re, im); break;
+        case 3: reg_inner_x<3>(l, x, zl, re, im); break;
+        case 4: reg_inner_x<4>(l, x, zl, re, im); break;
+        case 5: reg_inner_x<5>(l, x, zl, re, im); break;
+        case 6: reg_inner_x<6>(l, x, zl, re, im); break;
+        default: reg_inner_x<7>(l, x, zl, re, im); break;
     }
 }
 
@@ -128,6 +161,7 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
     V *lam = reinterpret_cast<V *>(in.lam);
     uint64_t tbase = (uint64_t)w << rec.W;
     for (int j = 0; j < rec.khi; ++j) tbase = ins0(tbase, rec.qhi[j]);
+    for (int i = threadIdx.x; i < kSegMaxGates * 4 * 2; i += blockDim.x) gsum[i] = 0.0;
     if (threadIdx.x < 128) {
         const uint32_t h = threadIdx.x >> 6, r = threadIdx.x & 63;
         uint64_t x = 0;
@@ -165,22 +199,63 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
     const R *mats = reinterpret_cast<const R *>(d.mats);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nred = 0;
-    for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) {
-        const SegGate G = d.segs[sg];
-        double re = 0.0, im = 0.0;
-        if (G.k == 1) seg_gate<1, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
-        else seg_gate<2, R>(G, adj, rec.tb, mats + 2 * G.mat, tp, tl, &re, &im);
-        if (adj && G.slot >= 0) {
-            re = wave_sum64(re);
-            im = wave_sum64(im);
-            if (lane == 0) {
-                gsum[(nred * 4 + wave) * 2] = re;
-                gsum[(nred * 4 + wave) * 2 + 1] = im;
+    // sweeps: each thread loads 8-amplitude groups over the sweep's three
+    // tile bits once, applies the sweep's gates in registers in order (taking
+    // each inner product right before its gate), and writes the group back
+    const uint32_t groups = 1u << (rec.tb - 3);
+    for (uint32_t sw = rec.sw0; sw < rec.sw1; ++sw) {
+        const SegSweep SW = d.sweeps[sw];
+        uint32_t off[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            off[j] = ((j & 1) ? (1u << SW.b[0]) : 0u) | ((j & 2) ? (1u << SW.b[1]) : 0u) |
+                     ((j & 4) ? (1u << SW.b[2]) : 0u);
+        for (uint32_t g0 = 0; g0 < groups; g0 += blockDim.x) {
+            const uint32_t g = g0 + threadIdx.x;
+            const bool act = g < groups;
+            uint32_t base = 0;
+            V x[8], l[8];
+            if (act) {
+                base = (uint32_t)ins0(ins0(ins0(g, SW.b[0]), SW.b[1]), SW.b[2]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) x[j] = tp[base | off[j]];
+                if (adj) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) l[j] = tl[base | off[j]];
+                }
             }
-            ++nred;
+            int p = SW.p0;
+            for (uint32_t gi = SW.g0; gi < SW.g1; ++gi) {
+                const SegGate G = d.segs[gi];
+                if (adj && G.slot >= 0) {
+                    double re = 0.0, im = 0.0;
+                    if (act) reg_inner(l, x, G.xl, G.zl, &re, &im);
+                    re = wave_sum64(re);
+                    im = wave_sum64(im);
+                    if (lane == 0) {
+                        gsum[(p * 4 + wave) * 2] += re;
+                        gsum[(p * 4 + wave) * 2 + 1] += im;
+                    }
+                    ++p;
+                }
+                if (act) {
+                    const R *m = mats + 2 * G.mat;
+                    reg_apply(G, x, m);
+                    if (adj) reg_apply(G, l, m);
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) tp[base | off[j]] = x[j];
+                if (adj) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) tl[base | off[j]] = l[j];
+                }
+            }
         }
         __syncthreads();
     }
+    for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) nred += (adj && d.segs[sg].slot >= 0);
     // one partial per inner product: its four waves in a fixed order
     if (adj && nred) {
         int idx = 0;
