@@ -100,3 +100,36 @@ def test_init_state_copy():
     assert abs(e[0] - ew) <= 1e-10 and np.max(np.abs(g[0] - gw)) <= 1e-10
     ew, gw = oracle.adjoint_grad(n, gates, th[1], H)
     assert abs(e[1] - ew) <= 1e-10 and np.max(np.abs(g[1] - gw)) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["c128", "c64"])
+def test_two_qubit_generators_unsorted_and_high_qubits(dtype):
+    """Parametrised XX / YY / ZZ rotations (Y phases, two-letter generators),
+    unsorted qubit lists and gates reaching the top qubits, across several
+    segments and sweeps."""
+    from circuits import Gate
+    n = 13
+    rng = np.random.default_rng(11)
+    gates = []
+    for layer in range(3):
+        for q in rng.permutation(n):
+            gates.append(Gate(["rx", "ry", "rz"][int(rng.integers(3))], (int(q),), param=len(gates),
+                              coeff=float(rng.uniform(0.5, 1.5))))
+        for i in range(n):
+            a, b = int(rng.integers(n)), int(rng.integers(n))
+            if a == b:
+                continue
+            gates.append(Gate(["rxx", "ryy", "rzz"][(i + layer) % 3], (a, b), param=len(gates), coeff=-0.7))
+        gates.append(Gate("cz", (n - 1, 2)))
+        gates.append(Gate("cx", (n - 2, 0)))
+    P = len(gates)
+    thetas = [rng.uniform(-np.pi, np.pi, P) for _ in range(3)]
+    H = [PauliTerm(0.9, ((0, "Y"), (n - 1, "X"))), PauliTerm(-0.4, ((5, "Z"), (7, "Z"))), PauliTerm(0.3, ((11, "Y"),))]
+    tol = TOL[dtype]
+    for mode in MODES:
+        b = cast.Batch([gates] * 3, [n] * 3, [P] * 3, [H] * 3, dtype=dtype, mode=mode)
+        e, g = b.run(thetas)
+        for i in range(3):
+            ew, gw = oracle.adjoint_grad(n, gates, thetas[i], H)
+            assert abs(e[i] - ew) <= tol, (mode, i)
+            assert np.max(np.abs(g[i] - gw)) <= tol, (mode, i, np.max(np.abs(g[i] - gw)))
