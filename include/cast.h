@@ -188,7 +188,9 @@ void fused_destroy(cast_fused *f);
  * kernel 0/1), "mfma_min_d" (smallest block dimension for the matrix cores,
  * 4..7; 7 disables them), "mfma_grid_per_cu", "mfma_direct_min_q",
  * "diag_unroll" (diagonal kernel chunks per thread: 1, 2, 4, 8),
- * "diag_max_grid", "diag_lds_table" (phases in LDS 1 / read from L1 0).
+ * "diag_max_grid", "diag_lds_table" (phases in LDS 1 / read from L1 0),
+ * "diag_order" (active tiles of the diagonal kernel visited pattern-fastest 0 /
+ * pattern-major 1).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

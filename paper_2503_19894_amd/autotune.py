@@ -38,6 +38,7 @@ KNOB_CHOICES = [
     ("diag_unroll", [2, 4, 8]),
     ("diag_max_grid", [1 << 14, 1 << 16, 1 << 18, 1 << 20]),
     ("diag_lds_table", [0, 1]),
+    ("diag_order", [0, 1]),
 ]
 
 

@@ -41,6 +41,7 @@ Tuning &tuning() {
         env("CAST_DIAG_UNROLL", x.diag_unroll);
         env("CAST_DIAG_MAX_GRID", x.diag_max_grid);
         env("CAST_DIAG_LDS_TABLE", x.diag_lds_table);
+        env("CAST_DIAG_ORDER", x.diag_order);
         env("CAST_MFMA_MIN_D", x.mfma_min_d);
         env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
         env("CAST_MFMA_DIRECT_MIN_Q", x.mfma_direct_min_q);
@@ -380,6 +381,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "diag_unroll") { *lo = 1; *hi = 8; return &t.diag_unroll[i]; }
     if (key == "diag_max_grid") { *lo = 256; return &t.diag_max_grid[i]; }
     if (key == "diag_lds_table") { *hi = 1; return &t.diag_lds_table[i]; }
+    if (key == "diag_order") { *hi = 1; return &t.diag_order[i]; }
     if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
     if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu[i]; }
     if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }

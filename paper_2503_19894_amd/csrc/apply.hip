@@ -163,9 +163,26 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
 // ------------------------------------------------------------------ diagonal
 // A diagonal gate (d = 0) multiplies amplitude x by D[j(x)], j(x) = the bits
 // of x at the targets.  Lanes stream consecutive 16-byte chunks of the state
-// whatever the targets are, so every access is coalesced; a lane whose
-// amplitudes all have D[j] = 1 issues neither the load nor the store, and
-// whole cache lines of such amplitudes never leave HBM.
+// whatever the targets are, so every access is coalesced.  Identity phases
+// are skipped per 128-byte line: a line (8 consecutive lanes) none of whose
+// amplitudes has D[j] != 1 is neither loaded nor stored, and a line with any
+// such amplitude is loaded and stored whole, so HBM never sees a partial-line
+// write (which it would have to complete by read-modify-write).
+//
+// Work is cut into tiles of 256 * U chunks, and a tile all of whose
+// amplitudes have identity phases is never visited: the host lists the
+// patterns of the high target bits that select an active tile, and the grid
+// walks only those tiles.  Workgroups are dealt to the chip's 8 XCDs
+// round-robin, so a plain tile = workgroup mapping can put the tiles of an
+// address-bit pattern on a few XCDs; tile number t is given to the XCD equal
+// to the XOR of its 3-bit digits, which spreads the tiles evenly.
+__device__ __forceinline__ uint64_t xcd_spread(uint64_t it) {
+    const uint64_t r = it >> 3;
+    uint64_t f = 0;
+    for (uint64_t y = r; y; y >>= 3) f ^= y;
+    return (r << 3) | ((it ^ f) & 7);
+}
+
 template <typename R, int U, bool LDS_TABLE>
 __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__restrict__ table, DiagArgs a) {
     using V = typename Amp<R>::T;
@@ -185,10 +202,11 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
         __syncthreads();
     }
     native_u4 *p16 = reinterpret_cast<native_u4 *>(psi_r);
+    const int line0 = (int)(threadIdx.x & 56);   // first lane of this lane's 128-byte line
     // j(x) = bits of amplitude x at the targets.  In the main loop a chunk's
-    // amplitude index is (uniform iteration base) + (threadIdx.x << S) + h with
+    // amplitude index is (uniform tile base) + (threadIdx.x << S) + h with
     // the base a multiple of 256 << S, so j splits into a per-lane part
-    // (computed once) and a wave-uniform part (one scalar pass per iteration).
+    // (computed once) and a wave-uniform part (one scalar pass per tile).
     auto jof = [&](uint64_t x) {
         uint32_t j = 0;
         for (int i = 0; i < a.k; ++i) j |= (uint32_t)((x >> a.q[i]) & 1u) << i;
@@ -198,26 +216,34 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
 #pragma unroll
     for (int h = 0; h < A; ++h) jl[h] = jof(((uint64_t)threadIdx.x << S) | (uint64_t)h);
     constexpr uint64_t per = 256ull * U;
-    const uint64_t nfull = a.nchunks / per;
-    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
+    const bool spread = (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
+    for (uint64_t it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
+        const uint32_t t = (uint32_t)(spread ? xcd_spread(it) : it);   // ntiles <= 2^24
+        uint32_t rest, pat;
+        if (a.pattern_major) {
+            rest = t & ((1u << a.rest_bits) - 1);
+            pat = t >> a.rest_bits;
+        } else {
+            rest = t / a.npat;
+            pat = t - rest * a.npat;
+        }
+        const uint64_t tile = deposit(rest, a.hlowmask, a.kh) | a.patoff[pat];
         native_u4 w[U];
         uint32_t ju[U];
         bool act[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t c0 = it * per + (uint64_t)u * 256;       // uniform
+            const uint64_t c0 = tile * per + (uint64_t)u * 256;     // uniform
             ju[u] = jof(c0 << S);
-            const uint64_t c = c0 + threadIdx.x;
             bool any = false;
 #pragma unroll
             for (int h = 0; h < A; ++h) any |= (a.amask >> (ju[u] | jl[h])) & 1u;
-            act[u] = any;
-            if (any) w[u] = __builtin_nontemporal_load(p16 + c);
+            act[u] = ((__ballot(any) >> line0) & 0xffull) != 0;
+            if (act[u]) w[u] = __builtin_nontemporal_load(p16 + c0 + threadIdx.x);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!act[u]) continue;
-            const uint64_t c = it * per + (uint64_t)u * 256 + threadIdx.x;
             V *v = reinterpret_cast<V *>(&w[u]);
 #pragma unroll
             for (int h = 0; h < A; ++h) {
@@ -230,11 +256,13 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
                     v[h].y = im;
                 }
             }
-            __builtin_nontemporal_store(w[u], p16 + c);
+            __builtin_nontemporal_store(w[u], p16 + tile * per + (uint64_t)u * 256 + threadIdx.x);
         }
     }
-    for (uint64_t c = nfull * per + (uint64_t)blockIdx.x * 256 + threadIdx.x; c < a.nchunks;
-         c += (uint64_t)gridDim.x * 256) {
+    // a state smaller than one tile: one chunk per lane (8-lane groups are
+    // still whole lines)
+    if (a.ntiles) return;
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < a.nchunks; c += (uint64_t)gridDim.x * 256) {
         bool any = false;
         uint32_t js[A];
 #pragma unroll
@@ -242,7 +270,7 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
             js[h] = jof((c << S) | (uint64_t)h);
             any |= (a.amask >> js[h]) & 1u;
         }
-        if (!any) continue;
+        if (((__ballot(any) >> line0) & 0xffull) == 0) continue;
         native_u4 w = p16[c];
         V *v = reinterpret_cast<V *>(&w);
 #pragma unroll
@@ -824,7 +852,42 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         g.nchunks = ((uint64_t)1 << n) * amp_bytes(dt) / 16;
         if (g.nchunks == 0) g.nchunks = 1;   // c64, n = 1: one chunk holds both amplitudes
         const int U = tu.diag_unroll[dt];
-        uint64_t grid = (g.nchunks + 256ull * U - 1) / (256ull * U);
+        const uint64_t per = 256ull * U;
+        uint64_t grid = (g.nchunks + per - 1) / per;
+        if (g.nchunks >= per) {
+            // tile = 2^tb amplitudes; targets >= tb select tiles
+            const int S = dt == CAST_C128 ? 0 : 1;   // log2(amplitudes per chunk)
+            int tb = S;
+            while ((1ull << (tb - S)) < per) ++tb;
+            int kl = 0;
+            while (kl < k && p.q[kl] < tb) ++kl;
+            const int kha = k - kl;
+            // does any amplitude of a tile whose high-target bits are ph have a phase != 1?
+            const uint64_t lo = kl == 6 ? ~0ull : (1ull << (1u << kl)) - 1;
+            auto active = [&](uint32_t ph) { return ((g.amask >> (ph << kl)) & lo) != 0; };
+            // keep the high targets the activity depends on
+            int rel[6], nrel = 0;
+            for (int i = 0; i < kha; ++i) {
+                bool matters = false;
+                for (uint32_t ph = 0; ph < (1u << kha) && !matters; ++ph) matters = active(ph) != active(ph ^ (1u << i));
+                if (matters) rel[nrel++] = i;
+            }
+            g.kh = nrel;
+            for (int j = 0; j < nrel; ++j) g.hlowmask[j] = (1ull << (p.q[kl + rel[j]] - tb)) - 1;
+            g.rest_bits = (n - tb) - nrel;
+            g.pattern_major = tu.diag_order[dt];
+            int npat = 0;
+            for (uint32_t pr = 0; pr < (1u << nrel); ++pr) {
+                uint32_t ph = 0, off = 0;
+                for (int j = 0; j < nrel; ++j)
+                    if ((pr >> j) & 1u) ph |= 1u << rel[j], off |= 1u << (p.q[kl + rel[j]] - tb);
+                if (active(ph)) g.patoff[npat++] = off;
+            }
+            g.npat = (uint32_t)npat;
+            g.ntiles = (uint64_t)npat << g.rest_bits;
+            grid = g.ntiles;
+            if (grid == 0) return CAST_OK;   // every phase is 1
+        }
         if (grid > (uint64_t)tu.diag_max_grid[dt]) grid = tu.diag_max_grid[dt];
         if (dt == CAST_C128) e = launch_diag<double>(U, tu.diag_lds_table[dt] != 0, (double *)psi, (const double *)dmat, g, (int)grid, stream);
         else e = launch_diag<float>(U, tu.diag_lds_table[dt] != 0, (float *)psi, (const float *)dmat, g, (int)grid, stream);

@@ -74,6 +74,7 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int diag_unroll[3] = {0, 4, 4};  // diagonal kernel: 16-byte chunks per thread per iteration
     int diag_max_grid[3] = {0, 1 << 20, 1 << 20};
     int diag_lds_table[3] = {0, 1, 1};   // diagonal kernel: phases staged in LDS (else read from L1)
+    int diag_order[3] = {0, 1, 1};       // diagonal kernel: 0 pattern-fastest, 1 pattern-major tile order
     int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels
     int mfma_grid_per_cu[3] = {0, 4, 4};
     int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather

@@ -28,6 +28,21 @@ struct DiagArgs {
     uint64_t nchunks;       // 16-byte chunks in the state
     int k;
     int q[6];               // sorted targets
+    // Tiles of 256 * U chunks; only tiles whose high-target bits (targets at
+    // or above the tile size on which the activity depends) form an active
+    // pattern are visited.  Tile number a splits into a pattern and the other
+    // tile bits, which are deposited around those targets: pattern-fastest
+    // order (a mod npat, a / npat) keeps tiles of every pattern in flight at
+    // once, pattern-major order (a >> rest_bits, a & (2^rest_bits - 1)) walks
+    // one pattern's tiles in address order.  ntiles = 0: the state is smaller
+    // than one tile and is walked chunk by chunk.
+    uint64_t ntiles;        // active tiles = npat << rest_bits
+    uint64_t hlowmask[6];   // per selecting target (ascending): bits of the tile index below it
+    int kh;                 // selecting targets
+    int rest_bits;
+    int pattern_major;
+    uint32_t npat;          // active patterns
+    uint32_t patoff[64];    // tile-index bits of each active pattern
 };
 
 }  // namespace cast
