@@ -175,6 +175,40 @@ cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *f, float *pass_ms
 cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt, int *kernel, int *d,
                             double *alg_bytes, double *flops);
 
+/* ------------------------------------------------------------ cache-blocked passes */
+
+/* Applies a fused list with several fused gates per HBM pass (cache
+ * blocking).  Consecutive fused gates are grouped into segments: a segment
+ * has a tile qubit set T = [0, w) plus up to tile_bits - w higher qubits
+ * (w >= 4), every non-diagonal gate of the segment mixes only amplitudes that
+ * differ on T (the qubits its non-identity blocks span; its other targets may
+ * lie anywhere), and diagonal gates join any segment.  One workgroup loads
+ * the 2^tile_bits amplitudes that agree off T into LDS, applies the segment's
+ * gates in order and writes them back, so a segment costs one read and one
+ * write of the state.  Gates with blocks larger than 8 x 8 (d >= 4) and
+ * segments of one gate run as the ordinary passes of apply_circuit.  The
+ * result equals apply_circuit's up to rounding.  The grouping is built on
+ * first use for the state's dtype with the "blocked_tile_bits" knob
+ * (log2 amplitudes per tile; 2^tile_bits amplitudes must fit 128 KiB) and
+ * cached in the fused list; device memory for it is owned by the list.
+ * Queued on the state's stream; not thread-safe on one fused list. */
+cast_status apply_circuit_blocked(cast_sv *sv, const cast_fused *f);
+
+/* Same, with a HIP event pair around every HBM pass; pass_ms receives one
+ * float (ms) per pass (blocked_info's count).  Synchronous.  For measurement. */
+cast_status apply_circuit_blocked_timed(cast_sv *sv, const cast_fused *f, float *pass_ms);
+
+/* Number of HBM passes of the grouping for a 2^n state of dtype dt (builds
+ * and caches the grouping, uploading the list's matrices if needed). */
+cast_status blocked_info(const cast_fused *f, int n, cast_dtype dt, size_t *n_passes);
+
+/* Pass i of that grouping: the fused gates [first, first + count) it covers,
+ * and for a segment its tile_bits, window w and high tile qubits
+ * (high_qubits: NULL or 10 ints, -1 past the last); tile_bits = window = 0
+ * for an ordinary one-gate pass.  CAST_EINVAL for i out of range. */
+cast_status blocked_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
+                              int *tile_bits, int *window, int *high_qubits);
+
 /* Frees a fused list.  NULL-safe.  The caller must not destroy a list while
  * work that uses it is still queued (synchronise the stream first). */
 void fused_destroy(cast_fused *f);
@@ -190,7 +224,8 @@ void fused_destroy(cast_fused *f);
  * "diag_unroll" (diagonal kernel chunks per thread: 1, 2, 4, 8),
  * "diag_max_grid", "diag_lds_table" (phases in LDS 1 / read from L1 0),
  * "diag_order" (active tiles of the diagonal kernel visited pattern-fastest 0 /
- * pattern-major 1).
+ * pattern-major 1), "blocked_tile_bits" (log2 amplitudes per tile of the
+ * cache-blocked passes, 8..13 for complex128, 8..14 for complex64).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

@@ -71,6 +71,13 @@ SIGNATURES = {
     "apply_circuit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "fused_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _c_int_p,
                                        _c_int_p, _c_double_p, _c_double_p]),
+    "apply_circuit_blocked": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "apply_circuit_blocked_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.POINTER(ctypes.c_float)]),
+    "blocked_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "blocked_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                         _c_int_p, _c_int_p, _c_int_p]),
     "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
                                     ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
@@ -213,14 +220,14 @@ def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, aggl
 # --------------------------------------------------------------------- tuning
 TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "max_grid", "use_diag", "mfma_min_d",
                "mfma_grid_per_cu", "mfma_direct_min_q", "diag_unroll", "diag_max_grid", "diag_lds_table",
-               "diag_order")
+               "diag_order", "blocked_tile_bits")
 #: environment overrides (set for sweeps) take precedence over the tuning file
 _ENV_OF = {"direct_min_q": "CAST_DIRECT_MIN_Q", "tile_bits": "CAST_TILE_BITS", "direct_ipt": "CAST_DIRECT_IPT",
            "direct_nt": "CAST_DIRECT_NT", "max_grid": "CAST_MAX_GRID", "use_diag": "CAST_USE_DIAG",
            "mfma_min_d": "CAST_MFMA_MIN_D", "mfma_grid_per_cu": "CAST_MFMA_GRID_PER_CU",
            "mfma_direct_min_q": "CAST_MFMA_DIRECT_MIN_Q", "diag_unroll": "CAST_DIAG_UNROLL",
            "diag_max_grid": "CAST_DIAG_MAX_GRID", "diag_lds_table": "CAST_DIAG_LDS_TABLE",
-           "diag_order": "CAST_DIAG_ORDER"}
+           "diag_order": "CAST_DIAG_ORDER", "blocked_tile_bits": "CAST_BLOCKED_TILE_BITS"}
 TUNING_FILE = os.path.join(_HERE, "tuning_gfx950.json")
 
 
@@ -291,6 +298,24 @@ class FusedCircuit:
                         ctypes.byref(f))
         return {"kernel": kern.value, "d": d.value, "alg_bytes": b.value, "flops": f.value}
 
+    def blocked_passes(self, dtype):
+        """The cache-blocked grouping on this circuit's n qubits in `dtype`:
+        one dict per HBM pass with the fused gates it covers and, for a
+        segment, its tile geometry (tile_bits = 0 for an ordinary pass)."""
+        dt = C128 if dtype == torch.complex128 else C64
+        np_ = ctypes.c_size_t()
+        blocked_info(self.handle, self.n, dt, ctypes.byref(np_))
+        out = []
+        for i in range(np_.value):
+            first, count = ctypes.c_size_t(), ctypes.c_size_t()
+            tb, w = ctypes.c_int(), ctypes.c_int()
+            hq = (ctypes.c_int * 10)()
+            blocked_pass_info(self.handle, self.n, dt, i, ctypes.byref(first), ctypes.byref(count), ctypes.byref(tb),
+                              ctypes.byref(w), hq)
+            out.append({"first": first.value, "count": count.value, "tile_bits": tb.value, "window": w.value,
+                        "high_qubits": tuple(q for q in hq if q >= 0)})
+        return out
+
     def __len__(self):
         return self.info()["n_fused"]
 
@@ -333,6 +358,17 @@ class StateVector:
         out = (ctypes.c_float * max(1, nf))()
         apply_circuit_timed(self.handle, fused.handle, out)
         return np.array(out[:nf], dtype=np.float64)
+
+    def apply_circuit_blocked(self, fused: FusedCircuit):
+        """Applies the circuit with several fused gates per HBM pass."""
+        apply_circuit_blocked(self.handle, fused.handle)
+
+    def apply_circuit_blocked_timed(self, fused: FusedCircuit):
+        """Applies the circuit cache-blocked; returns per-HBM-pass device times (ms)."""
+        npass = len(fused.blocked_passes(self.tensor.dtype))
+        out = (ctypes.c_float * max(1, npass))()
+        apply_circuit_blocked_timed(self.handle, fused.handle, out)
+        return np.array(out[:npass], dtype=np.float64)
 
     def expval(self, terms):
         arr = pauli_terms(terms)

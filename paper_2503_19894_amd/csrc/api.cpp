@@ -45,6 +45,7 @@ Tuning &tuning() {
         env("CAST_MFMA_MIN_D", x.mfma_min_d);
         env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
         env("CAST_MFMA_DIRECT_MIN_Q", x.mfma_direct_min_q);
+        env("CAST_BLOCKED_TILE_BITS", x.blocked_tile_bits);
         return x;
     }();
     return t;
@@ -131,23 +132,38 @@ static void pack(const PassPlan &p, std::vector<R> &dst) {
     pack_plan<R>(p, dst);
 }
 
-cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
-                         std::vector<size_t> *offsets) {
+// Every plan's matrices, cast to the state dtype, one after another with each
+// plan's start 256-byte aligned (for scalar loads); offsets in reals.
+static size_t pack_all(const std::vector<PassPlan> &ps, cast_dtype dt, std::vector<double> &hd,
+                       std::vector<float> &hf, std::vector<size_t> *offsets) {
     offsets->clear();
-    std::vector<double> hd;
-    std::vector<float> hf;
     size_t elems = 0;
     for (const PassPlan &p : ps) {
-        offsets->push_back(elems);  // in reals of the dtype
+        offsets->push_back(elems);
         if (dt == CAST_C128) pack<double>(p, hd), elems = hd.size();
         else pack<float>(p, hf), elems = hf.size();
-        // keep every plan's matrices 256-byte aligned for scalar loads
         const size_t align = 256 / (dt == CAST_C128 ? 8 : 4);
         while (elems % align) {
             if (dt == CAST_C128) hd.push_back(0); else hf.push_back(0);
             ++elems;
         }
     }
+    return elems;
+}
+
+std::vector<size_t> plan_offsets(const std::vector<PassPlan> &ps, cast_dtype dt) {
+    std::vector<double> hd;
+    std::vector<float> hf;
+    std::vector<size_t> off;
+    pack_all(ps, dt, hd, hf, &off);
+    return off;
+}
+
+cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
+                         std::vector<size_t> *offsets) {
+    std::vector<double> hd;
+    std::vector<float> hf;
+    const size_t elems = pack_all(ps, dt, hd, hf, offsets);
     const size_t bytes = elems * (dt == CAST_C128 ? 8 : 4);
     cast_status st = dev_alloc(&out->ptr, bytes);
     if (st) return st;
@@ -385,6 +401,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
     if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu[i]; }
     if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }
+    if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 14 : 13; return &t.blocked_tile_bits[i]; }
     return nullptr;
 }
 
@@ -577,7 +594,7 @@ cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt,
 
 void fused_destroy(cast_fused *f) {
     if (!f) return;
-    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr);
+    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr), blocked_free(f->blocked[d]);
     delete f;
 }
 

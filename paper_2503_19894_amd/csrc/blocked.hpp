@@ -1,0 +1,47 @@
+// Cache-blocked execution of a fused gate list: several fused gates per HBM
+// pass.
+//
+// Consecutive fused gates are grouped into segments.  A segment has a tile
+// qubit set T = [0, w) + H (w >= 4 low "window" qubits and up to tb - w higher
+// qubits H, |T| = tb); every non-diagonal gate of the segment mixes only
+// amplitudes that differ on T (its block span, the qubits touched by its first
+// d virtual basis vectors, lies in T).  A tile is the 2^tb amplitudes that
+// agree off T: 2^|H| contiguous runs of 2^w amplitudes.  One workgroup loads a
+// tile into LDS, applies the segment's gates in order (block gates by coset of
+// their span, diagonal gates elementwise, with the targets outside T read off
+// the tile's base index), and writes it back, so a segment costs one read and
+// one write of the state however many gates it holds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cast {
+
+constexpr int kBlkMaxHigh = 10;    // tile qubits above the window
+constexpr int kBlkMaxD = 3;        // largest block dimension applied inside a tile
+constexpr int kBlkMinWindow = 4;   // smallest window: runs of >= 16 amplitudes
+
+struct BlkGate {             // one fused gate inside a tile
+    int kind;                // 0 diagonal (d = 0), 1 blocks of 2^d x 2^d
+    int k, d;
+    int q[6];                // sorted targets
+    int tpos[6];             // tile bit of each target, -1 when the target is outside the tile
+    uint32_t colv[6];        // virtual coordinates of local index bit s (the columns of L^-1)
+    uint32_t span[kBlkMaxD]; // tile offset of virtual basis vector i < d
+    uint32_t pivlow[kBlkMaxD];   // coset enumeration: (1 << pivot) - 1 per pivot bit, ascending
+    int8_t slot[32];         // block id -> index among the active blocks, -1: identity block
+    uint64_t amask;          // diagonal: local indices whose phase is not 1
+    uint64_t mat;            // offset (reals) of the gate's matrices in the fused list's buffer
+};
+
+struct BlkSeg {              // kernel arguments of one segment pass
+    uint64_t ntiles;         // 2^(n - tb)
+    uint64_t hlowmask[kBlkMaxHigh];  // per high tile qubit (ascending): global index bits below it
+    int tb, w, nh;
+    int qh[kBlkMaxHigh];     // high tile qubits, ascending
+    uint32_t g0, g1;         // gates [g0, g1) of the gate table
+};
+
+}  // namespace cast

@@ -78,6 +78,7 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels
     int mfma_grid_per_cu[3] = {0, 4, 4};
     int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather
+    int blocked_tile_bits[3] = {0, 13, 12};  // cache-blocked passes: log2(amplitudes per LDS tile)
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).
@@ -116,6 +117,8 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
 cast_status upload_plan(const PassPlan &p, cast_dtype dt, DeviceMatrix *out);
 cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
                          std::vector<size_t> *offsets);
+// The offsets (in reals) upload_plans gives each plan, computed on the host.
+std::vector<size_t> plan_offsets(const std::vector<PassPlan> &ps, cast_dtype dt);
 
 // Device allocation with the CAST_MAX_DEVICE_BYTES cap.
 cast_status dev_alloc(void **ptr, size_t bytes);
@@ -145,6 +148,11 @@ struct cast_sv {
     bool owns = false;
 };
 
+namespace cast {
+struct BlockedPlan;                  // cache-blocked grouping of a fused list (blocked.cpp)
+void blocked_free(BlockedPlan *b);
+}  // namespace cast
+
 struct cast_fused {
     int n = 0;
     std::vector<cast::PassPlan> plans;
@@ -152,4 +160,6 @@ struct cast_fused {
     // device copies of the block matrices, per dtype (lazily uploaded)
     cast::DeviceMatrix dev[3];
     std::vector<size_t> dev_off[3];
+    // cache-blocked grouping, per dtype (built on first use)
+    cast::BlockedPlan *blocked[3] = {nullptr, nullptr, nullptr};
 };

@@ -31,16 +31,18 @@ def inverse_qft(n):
     return inv
 
 
+@pytest.mark.parametrize("mode", ["per_pass", "blocked"])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
-def test_qft30_closed_form_and_inverse(dtype, tol):
+def test_qft30_closed_form_and_inverse(dtype, tol, mode):
     n = N_QUBITS
-    print(f"qft{n} {dtype}: generating input", flush=True)
+    print(f"qft{n} {dtype} {mode}: generating input", flush=True)
     psi = random_state_torch(n, seed=0, device="cuda", dtype=dtype)
     psi0 = psi.cpu().numpy().astype(np.complex128)
     sv = cast.StateVector(n, tensor=psi)
     fc = cast.FusedCircuit(n, qft(n), k_max=5)
-    print(f"  {len(fc)} fused passes; applying", flush=True)
-    sv.apply_circuit(fc)
+    apply = sv.apply_circuit if mode == "per_pass" else sv.apply_circuit_blocked
+    print(f"  {len(fc)} fused gates; applying", flush=True)
+    apply(fc)
     torch.cuda.synchronize()
     rng = np.random.default_rng(30)
     ys = [0, 1, (1 << n) - 1] + [int(y) for y in rng.integers(0, 1 << n, 2)]
@@ -51,7 +53,7 @@ def test_qft30_closed_form_and_inverse(dtype, tol):
         assert abs(g - want) <= tol
     print("  inverse", flush=True)
     inv = cast.FusedCircuit(n, inverse_qft(n), k_max=5)
-    sv.apply_circuit(inv)
+    apply(inv)
     torch.cuda.synchronize()
     err = float((psi.to(torch.complex128) - torch.from_numpy(psi0).to("cuda")).abs().max())
     print(f"  max |d amp| after QFT^-1 QFT: {err:.2e}", flush=True)
