@@ -225,7 +225,9 @@ void fused_destroy(cast_fused *f);
  * "diag_max_grid", "diag_lds_table" (phases in LDS 1 / read from L1 0),
  * "diag_order" (active tiles of the diagonal kernel visited pattern-fastest 0 /
  * pattern-major 1), "blocked_tile_bits" (log2 amplitudes per tile of the
- * cache-blocked passes, 8..13 for complex128, 8..14 for complex64).
+ * cache-blocked passes, 8..12 for complex128, 8..13 for complex64: tiles of
+ * at most 64 KiB, so two workgroups share a compute unit's LDS),
+ * "blocked_threads" (their workgroup size: 256, 512 or 1024).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

@@ -46,6 +46,7 @@ Tuning &tuning() {
         env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
         env("CAST_MFMA_DIRECT_MIN_Q", x.mfma_direct_min_q);
         env("CAST_BLOCKED_TILE_BITS", x.blocked_tile_bits);
+        env("CAST_BLOCKED_THREADS", x.blocked_threads);
         return x;
     }();
     return t;
@@ -401,7 +402,8 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
     if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu[i]; }
     if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }
-    if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 14 : 13; return &t.blocked_tile_bits[i]; }
+    if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 13 : 12; return &t.blocked_tile_bits[i]; }
+    if (key == "blocked_threads") { *lo = 256; *hi = 1024; return &t.blocked_threads[i]; }
     return nullptr;
 }
 
@@ -411,7 +413,8 @@ cast_status tuning_set(const char *key, cast_dtype dt, int value) {
     int *f = tuning_field(key, dt, &lo, &hi);
     if (!f) return fail(CAST_EINVAL, std::string("unknown tuning key ") + key);
     if (value < lo || value > hi || (std::string(key) == "direct_ipt" && value == 3) ||
-        (std::string(key) == "diag_unroll" && (value & (value - 1))))
+        (std::string(key) == "diag_unroll" && (value & (value - 1))) ||
+        (std::string(key) == "blocked_threads" && (value & (value - 1))))
         return fail(CAST_EINVAL, std::string("value out of range for ") + key);
     *f = value;
     return CAST_OK;

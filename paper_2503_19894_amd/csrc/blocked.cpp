@@ -65,6 +65,7 @@ BlkGate make_gate(const PassPlan &p, int w, const int *qh, int nh, uint64_t mat)
     g.k = p.k;
     g.d = p.d;
     g.mat = mat;
+    g.mat_reals = p.d == 0 ? 2u << p.k : (uint32_t)(2 * p.mat.size());
     for (int s = 0; s < p.k; ++s) {
         const int q = p.q[s];
         g.q[s] = q;
@@ -125,8 +126,8 @@ BlkGate make_gate(const PassPlan &p, int w, const int *qh, int nh, uint64_t mat)
 
 cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
     const int tb = tuning().blocked_tile_bits[dt];
-    if (((size_t)1 << tb) * amp_bytes(dt) > (128u << 10))
-        return fail(CAST_EINVAL, "blocked_tile_bits: tile exceeds 128 KiB of LDS");
+    if (((size_t)1 << tb) * amp_bytes(dt) > (64u << 10))
+        return fail(CAST_EINVAL, "blocked_tile_bits: tile exceeds 64 KiB of LDS");
     auto *bp = new BlockedPlan;
     bp->tb = tb;
     const int n = f.n;
@@ -157,6 +158,10 @@ cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
             s.g0 = (uint32_t)bp->gates.size();
             for (size_t i : cur) bp->gates.push_back(make_gate(P[i], w, s.qh, s.nh, off[i]));
             s.g1 = (uint32_t)bp->gates.size();
+            uint32_t mbytes = 0;
+            for (uint32_t gi = s.g0; gi < s.g1; ++gi)
+                mbytes = std::max<uint32_t>(mbytes, bp->gates[gi].mat_reals * (dt == CAST_C128 ? 8 : 4));
+            s.area = kBlkAreaHead + ((mbytes + 15) & ~15u);
             bp->passes.push_back(ps);
         }
         cur.clear();
@@ -168,7 +173,8 @@ cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
         if (p.identity()) continue;
         const uint64_t sp = span_qubits(p);
         int w;
-        if (n < tb || p.d > kBlkMaxD || !window_of(sp, tb, &w)) {
+        const size_t mchunks = ((p.d == 0 ? (2u << p.k) : 2 * p.mat.size()) * amp_bytes(dt) / 2 + 15) / 16;
+        if (n < tb || p.d > kBlkMaxD || mchunks > kBlkMaxMatChunks || !window_of(sp, tb, &w)) {
             // an ordinary pass of its own
             close(i);
             BlockedPlan::Pass ps;

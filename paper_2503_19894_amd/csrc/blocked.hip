@@ -29,40 +29,111 @@ __device__ __forceinline__ uint64_t deposit_bits(uint64_t g, const uint64_t *low
     return g;
 }
 
-// Global index of tile position y: window bits keep their place, tile bit
-// w + i is high qubit i.
-__device__ __forceinline__ uint64_t global_of(uint64_t tbase, uint32_t y, const BlkSeg &s) {
-    uint64_t x = tbase | (y & ((1u << s.w) - 1));
+// Global index bits of tile position y (without the tile's base): window
+// bits keep their place, tile bit w + i is high qubit i.  Like the coset
+// enumeration, the L^-1 map and the LDS swizzle, this map is linear over
+// GF(2), so the value at y = lane + uniform splits into a per-lane part
+// computed once and a wave-uniform part computed on the scalar unit.
+__device__ __forceinline__ uint64_t expand(uint32_t y, const BlkSeg &s) {
+    uint64_t x = y & ((1u << s.w) - 1);
     const uint32_t hi = y >> s.w;
     for (int i = 0; i < s.nh; ++i)
         if ((hi >> i) & 1u) x |= 1ull << s.qh[i];
     return x;
 }
 
-// Diagonal gate: amplitude y gets phase D[j], j = its bits at the targets.
-// y = threadIdx.x + 256 i, so the targets on tile bits < 8 give a per-lane
-// part of j and those on higher tile bits a part uniform per iteration.
-template <typename R, int S>
-__device__ __forceinline__ void diag_in_tile(typename Cx<R>::T *tile, const R *mats, const BlkGate &g,
-                                             uint32_t juni, int tb) {
-    using V = typename Cx<R>::T;
-    uint32_t jl = juni, lane_bits = 0;
-    for (int s = 0; s < g.k; ++s) {
-        const int p = g.tpos[s];
-        if (p >= 0 && p < 8) jl |= ((threadIdx.x >> p) & 1u) << s;
-        if (p >= 8) lane_bits |= 1u << s;
+// Virtual coordinates contributed by the in-tile targets of position y.
+__device__ __forceinline__ uint32_t virt(uint32_t y, const BlkGate &g) {
+    uint32_t u = 0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (s < g.k && g.tpos[s] >= 0 && ((y >> g.tpos[s]) & 1u)) u ^= g.colv[s];
+    return u;
+}
+
+// Local index bits contributed by the in-tile targets of position y.
+__device__ __forceinline__ uint32_t loc(uint32_t y, const BlkGate &g) {
+    uint32_t j = 0;
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (s < g.k && g.tpos[s] >= 0) j |= ((y >> g.tpos[s]) & 1u) << s;
+    return j;
+}
+
+// Loop iterations of the workgroup over a gate's work items (amplitudes for
+// a diagonal gate, cosets of the span for a block gate).
+template <int NT>
+__device__ __forceinline__ uint32_t iters_of(const BlkGate &g, uint32_t tile_amps) {
+    const uint32_t items = tile_amps >> (g.kind == 0 ? 0 : g.d);
+    return (items + NT - 1) / NT;
+}
+
+// Staging of a gate area in two halves: the matrices are read from global
+// memory into registers before the current gate is applied (so their
+// latency hides behind it) and written to LDS afterwards, together with the
+// slot table and the iteration table of this tile.
+struct Prefetch {
+    u4 m[kBlkMaxMatChunks / 256];
+};
+
+template <typename R, int NT>
+__device__ __forceinline__ void prefetch(Prefetch &pf, const R *mats, const BlkGate &g) {
+    const u4 *src = reinterpret_cast<const u4 *>(mats + g.mat);   // 256-byte aligned
+    const uint32_t n16 = (g.mat_reals * (uint32_t)sizeof(R) + 15) / 16;
+#pragma unroll
+    for (int r = 0; r < (int)((kBlkMaxMatChunks + NT - 1) / NT); ++r) {
+        const uint32_t i = threadIdx.x + r * NT;
+        if (i < n16) pf.m[r] = src[i];
     }
-    const V *tab = reinterpret_cast<const V *>(mats + g.mat);
-    const uint32_t iters = 1u << (tb - 8);
+}
+
+template <typename R, int S, int NT>
+__device__ __forceinline__ void commit(char *area, const Prefetch &pf, const BlkGate &g, uint64_t tbase,
+                                       uint32_t tile_amps) {
+    if (threadIdx.x < 32) reinterpret_cast<int8_t *>(area)[threadIdx.x] = g.slot[threadIdx.x];
+    u4 *dst = reinterpret_cast<u4 *>(area + kBlkAreaHead);
+    const uint32_t n16 = (g.mat_reals * (uint32_t)sizeof(R) + 15) / 16;
+#pragma unroll
+    for (int r = 0; r < (int)((kBlkMaxMatChunks + NT - 1) / NT); ++r) {
+        const uint32_t i = threadIdx.x + r * NT;
+        if (i < n16) dst[i] = pf.m[r];
+    }
+    // iteration i covers items i*NT + lane; its uniform part is item i*NT
+    if (threadIdx.x < iters_of<NT>(g, tile_amps)) {
+        uint32_t juni = 0, uuni = 0;   // targets outside the tile, fixed by the tile
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+            if (q < g.k && g.tpos[q] < 0 && ((tbase >> g.q[q]) & 1u)) juni |= 1u << q, uuni ^= g.colv[q];
+        const uint32_t i0 = threadIdx.x * NT;
+        uint2 e;
+        if (g.kind == 0) {
+            e.x = juni ^ loc(i0, g);
+            e.y = at<S>(i0);
+        } else {
+            uint32_t y = i0;
+            for (int i = 0; i < g.d; ++i) y = ((y & ~g.pivlow[i]) << 1) | (y & g.pivlow[i]);
+            e.x = uuni ^ virt(y, g);
+            e.y = at<S>(y);
+        }
+        reinterpret_cast<uint2 *>(area + kBlkIterOff)[threadIdx.x] = e;
+    }
+}
+
+// Diagonal gate: amplitude y gets phase D[j(y)], j = its bits at the targets.
+// Identity phases are exactly 1, so every amplitude is simply multiplied.
+template <typename R, int S, int NT>
+__device__ __forceinline__ void diag_in_tile(typename Cx<R>::T *tile, const char *area, const BlkGate &g,
+                                             uint32_t tile_amps) {
+    using V = typename Cx<R>::T;
+    const V *tab = reinterpret_cast<const V *>(area + kBlkAreaHead);
+    const uint2 *itab = reinterpret_cast<const uint2 *>(area + kBlkIterOff);
+    const uint32_t jl = loc(threadIdx.x, g);
+    const uint32_t al = at<S>(threadIdx.x);
+    const uint32_t iters = tile_amps / NT;
     for (uint32_t i = 0; i < iters; ++i) {
-        uint32_t j = jl;
-        if (lane_bits)
-            for (int s = 0; s < g.k; ++s)
-                if (g.tpos[s] >= 8) j |= ((i >> (g.tpos[s] - 8)) & 1u) << s;
-        if (!((g.amask >> j) & 1u)) continue;
-        const uint32_t y = threadIdx.x + (i << 8);
-        V &a = tile[at<S>(y)];
-        const V t = tab[j];
+        const uint2 e = itab[i];
+        V &a = tile[al ^ e.y];
+        const V t = tab[jl ^ e.x];
         const R re = a.x * t.x - a.y * t.y;
         const R im = a.x * t.y + a.y * t.x;
         a.x = re;
@@ -70,143 +141,177 @@ __device__ __forceinline__ void diag_in_tile(typename Cx<R>::T *tile, const R *m
     }
 }
 
-// Block gate with 2^D x 2^D blocks: one work item per coset of the span
-// (tile positions y with zeros at the pivot bits).  The item's virtual
-// coordinates u = L^-1 j give the block (u >> D) and the item's place in it
-// (u mod 2^D); identity blocks are skipped.
-template <int D, typename R, int S>
-__device__ __forceinline__ void block_in_tile(typename Cx<R>::T *tile, const R *mats, const BlkGate &g,
-                                              uint32_t uuni, int tb) {
+// Block gate with 2^D x 2^D blocks: one work item per coset of the span.
+// The item's virtual coordinates u = L^-1 j give its block (u >> D; identity
+// blocks are skipped) and its place in the block (u mod 2^D), from which the
+// block's first element follows.
+template <int D, typename R, int S, int NT>
+__device__ __forceinline__ void block_in_tile(typename Cx<R>::T *tile, const char *area, const BlkGate &g,
+                                              uint32_t tile_amps) {
     using V = typename Cx<R>::T;
     constexpr int N = 1 << D;
-    uint32_t off[N];
+    const int8_t *slot = reinterpret_cast<const int8_t *>(area);
+    const uint2 *itab = reinterpret_cast<const uint2 *>(area + kBlkIterOff);
+    const V *mt = reinterpret_cast<const V *>(area + kBlkAreaHead);
+    uint32_t soff[N], sspan[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) sspan[i] = at<S>(g.span[i]);
 #pragma unroll
     for (int c = 0; c < N; ++c) {
         uint32_t o = 0;
 #pragma unroll
         for (int i = 0; i < D; ++i)
-            if ((c >> i) & 1) o ^= g.span[i];
-        off[c] = o;
+            if ((c >> i) & 1) o ^= sspan[i];
+        soff[c] = o;
     }
-    const uint32_t items = 1u << (tb - D);
-    for (uint32_t it = threadIdx.x; it < items; it += 256) {
-        uint32_t y = it;
+    const uint32_t items = tile_amps >> D;
+    uint32_t ylane = threadIdx.x;
 #pragma unroll
-        for (int i = 0; i < D; ++i) y = ((y & ~g.pivlow[i]) << 1) | (y & g.pivlow[i]);
-        uint32_t u = uuni;
-        for (int s = 0; s < g.k; ++s)
-            if (g.tpos[s] >= 0 && ((y >> g.tpos[s]) & 1u)) u ^= g.colv[s];
-        const int sl = g.slot[u >> D];
+    for (int i = 0; i < D; ++i) ylane = ((ylane & ~g.pivlow[i]) << 1) | (ylane & g.pivlow[i]);
+    const uint32_t ul = virt(ylane, g);
+    const uint32_t al = at<S>(ylane);
+    const uint32_t iters = (items + NT - 1) / NT;
+    for (uint32_t i = 0; i < iters; ++i) {
+        if (i * NT + threadIdx.x >= items) break;
+        const uint2 e = itab[i];
+        const uint32_t u = ul ^ e.x;
+        const int sl = slot[u >> D];
         if (sl < 0) continue;
-        const uint32_t within = u & (N - 1);
-        uint32_t b = y;
+        uint32_t a0 = al ^ e.y;
 #pragma unroll
-        for (int i = 0; i < D; ++i)
-            if ((within >> i) & 1u) b ^= g.span[i];
-        const R *m = mats + g.mat + (size_t)sl * (2 * N * N);
+        for (int b = 0; b < D; ++b)
+            if ((u >> b) & 1u) a0 ^= sspan[b];
+        const V *m = mt + sl * N * N;
         V v[N];
 #pragma unroll
-        for (int c = 0; c < N; ++c) v[c] = tile[at<S>(b ^ off[c])];
+        for (int c = 0; c < N; ++c) v[c] = tile[a0 ^ soff[c]];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
             R ar = 0, ai = 0;
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-                const R mr = m[2 * (r * N + c)], mi = m[2 * (r * N + c) + 1];
-                ar = fma(mr, v[c].x, ar);
-                ar = fma(-mi, v[c].y, ar);
-                ai = fma(mr, v[c].y, ai);
-                ai = fma(mi, v[c].x, ai);
+                const V x = m[r * N + c];
+                ar = fma(x.x, v[c].x, ar);
+                ar = fma(-x.y, v[c].y, ar);
+                ai = fma(x.x, v[c].y, ai);
+                ai = fma(x.y, v[c].x, ai);
             }
             V o;
             o.x = ar;
             o.y = ai;
-            tile[at<S>(b ^ off[r])] = o;
+            tile[a0 ^ soff[r]] = o;
         }
     }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_blocked(R *__restrict__ psi_r, const R *__restrict__ mats,
-                                                 const BlkGate *__restrict__ gates, BlkSeg s) {
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) k_blocked(R *__restrict__ psi_r, const R *__restrict__ mats,
+                                                const BlkGate *__restrict__ gates, BlkSeg s) {
     using V = typename Cx<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;
+    constexpr int B = 8;                       // chunks in flight per lane
     extern __shared__ u4 lds16[];
     V *tile = reinterpret_cast<V *>(lds16);
+    const uint32_t tile_amps = 1u << s.tb;
+    char *area0 = reinterpret_cast<char *>(lds16) + (size_t)tile_amps * sizeof(V);
     u4 *p16 = reinterpret_cast<u4 *>(psi_r);
-    const uint32_t chunks = 1u << (s.tb - S);
+    const uint32_t chunks = tile_amps >> S;
+    const uint64_t glane = expand(threadIdx.x << S, s) >> S;
+    const uint32_t slane = swz(threadIdx.x);
     for (uint64_t t = blockIdx.x; t < s.ntiles; t += gridDim.x) {
         const uint64_t tbase = deposit_bits(t << s.w, s.hlowmask, s.nh);
-        // ---- load: 8 chunks in flight per lane
-        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
-            u4 buf[8];
+        u4 *base16 = p16 + (tbase >> S) + glane;
+        // ---- load (chunk c = c0 + lane)
+        for (uint32_t c0 = 0; c0 < chunks; c0 += B * NT) {
+            u4 buf[B];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * 256;
-                if (c < chunks) buf[u] = __builtin_nontemporal_load(p16 + (global_of(tbase, c << S, s) >> S));
+            for (int u = 0; u < B; ++u) {
+                const uint32_t c = c0 + u * NT;
+                if (c + threadIdx.x < chunks) buf[u] = __builtin_nontemporal_load(base16 + (expand(c << S, s) >> S));
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * 256;
-                if (c < chunks) lds16[swz(c)] = buf[u];
+            for (int u = 0; u < B; ++u) {
+                const uint32_t c = c0 + u * NT;
+                if (c + threadIdx.x < chunks) lds16[slane ^ swz(c)] = buf[u];
             }
         }
+        Prefetch pf;
+        prefetch<R, NT>(pf, mats, gates[s.g0]);
+        commit<R, S, NT>(area0, pf, gates[s.g0], tbase, tile_amps);
         __syncthreads();
-        // ---- the segment's gates, in order
+        // ---- the segment's gates, in order; the next gate is staged into
+        // the other area meanwhile
         for (uint32_t gi = s.g0; gi < s.g1; ++gi) {
             const BlkGate &g = gates[gi];
-            // contribution of the targets outside the tile (fixed by the tile)
-            uint32_t juni = 0, uuni = 0;
-            for (int q = 0; q < g.k; ++q)
-                if (g.tpos[q] < 0 && ((tbase >> g.q[q]) & 1u)) juni |= 1u << q, uuni ^= g.colv[q];
+            char *area = area0 + ((gi - s.g0) & 1u) * s.area;
+            const bool more = gi + 1 < s.g1;
+            if (more) prefetch<R, NT>(pf, mats, gates[gi + 1]);
             if (g.kind == 0) {
-                diag_in_tile<R, S>(tile, mats, g, juni, s.tb);
+                diag_in_tile<R, S, NT>(tile, area, g, tile_amps);
             } else {
                 switch (g.d) {
-                    case 1: block_in_tile<1, R, S>(tile, mats, g, uuni, s.tb); break;
-                    case 2: block_in_tile<2, R, S>(tile, mats, g, uuni, s.tb); break;
-                    default: block_in_tile<3, R, S>(tile, mats, g, uuni, s.tb); break;
+                    case 1: block_in_tile<1, R, S, NT>(tile, area, g, tile_amps); break;
+                    case 2: block_in_tile<2, R, S, NT>(tile, area, g, tile_amps); break;
+                    default: block_in_tile<3, R, S, NT>(tile, area, g, tile_amps); break;
                 }
             }
+            if (more) commit<R, S, NT>(area0 + ((gi + 1 - s.g0) & 1u) * s.area, pf, gates[gi + 1], tbase, tile_amps);
             __syncthreads();
         }
         // ---- store
-        for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
+        for (uint32_t c0 = 0; c0 < chunks; c0 += B * NT) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const uint32_t c = c0 + u * 256;
-                if (c < chunks) __builtin_nontemporal_store(lds16[swz(c)], p16 + (global_of(tbase, c << S, s) >> S));
+            for (int u = 0; u < B; ++u) {
+                const uint32_t c = c0 + u * NT;
+                if (c + threadIdx.x < chunks)
+                    __builtin_nontemporal_store(lds16[slane ^ swz(c)], base16 + (expand(c << S, s) >> S));
             }
         }
         __syncthreads();   // the next tile overwrites LDS
     }
 }
 
-template <typename R>
+template <typename R, int NT>
 hipError_t allow_lds() {
-    static hipError_t done = hipFuncSetAttribute((const void *)k_blocked<R>,
+    static hipError_t done = hipFuncSetAttribute((const void *)k_blocked<R, NT>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10);
     return done;
+}
+
+template <typename R, int NT>
+hipError_t launch_nt(R *psi, const R *mats, const BlkGate *gates, const BlkSeg &s, uint32_t grid, size_t lds,
+                     hipStream_t stream) {
+    const hipError_t ae = allow_lds<R, NT>();
+    if (ae != hipSuccess) return ae;
+    hipLaunchKernelGGL((k_blocked<R, NT>), dim3(grid), dim3(NT), lds, stream, psi, mats, gates, s);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_r(int nt, R *psi, const R *mats, const BlkGate *gates, const BlkSeg &s, uint32_t grid,
+                    size_t lds, hipStream_t stream) {
+    switch (nt) {
+        case 256: return launch_nt<R, 256>(psi, mats, gates, s, grid, lds, stream);
+        case 512: return launch_nt<R, 512>(psi, mats, gates, s, grid, lds, stream);
+        default: return launch_nt<R, 1024>(psi, mats, gates, s, grid, lds, stream);
+    }
 }
 
 }  // namespace
 
 cast_status launch_blocked(void *psi, cast_dtype dt, const void *mats, const BlkGate *gates, const BlkSeg &s,
                            hipStream_t stream) {
-    const size_t lds = ((size_t)1 << s.tb) * amp_bytes(dt);
-    if (lds > (128u << 10)) return fail(CAST_EUNSUPPORTED, "blocked tile exceeds 128 KiB of LDS");
-    const hipError_t ae = dt == CAST_C128 ? allow_lds<double>() : allow_lds<float>();
-    if (ae != hipSuccess) return fail(CAST_EHIP, std::string("LDS attribute: ") + hipGetErrorString(ae));
+    const size_t tile = ((size_t)1 << s.tb) * amp_bytes(dt);
+    const size_t lds = tile + 2 * (size_t)s.area;
+    if (lds > (128u << 10)) return fail(CAST_EUNSUPPORTED, "blocked tile and gate areas exceed 128 KiB of LDS");
+    int nt = tuning().blocked_threads[dt];
+    while (nt > 256 && ((size_t)1 << s.tb) < (size_t)nt) nt >>= 1;   // at least one amplitude per thread
     uint64_t grid = s.ntiles;
     const uint64_t cap = (uint64_t)tuning().max_grid[dt];
     if (grid > cap) grid = cap;
-    if (dt == CAST_C128)
-        hipLaunchKernelGGL(k_blocked<double>, dim3((uint32_t)grid), dim3(256), lds, stream, (double *)psi,
-                           (const double *)mats, gates, s);
-    else
-        hipLaunchKernelGGL(k_blocked<float>, dim3((uint32_t)grid), dim3(256), lds, stream, (float *)psi,
-                           (const float *)mats, gates, s);
-    const hipError_t e = hipGetLastError();
+    const hipError_t e = dt == CAST_C128
+        ? launch_r<double>(nt, (double *)psi, (const double *)mats, gates, s, (uint32_t)grid, lds, stream)
+        : launch_r<float>(nt, (float *)psi, (const float *)mats, gates, s, (uint32_t)grid, lds, stream);
     if (e != hipSuccess) return fail(CAST_EHIP, std::string("blocked pass launch: ") + hipGetErrorString(e));
     return CAST_OK;
 }

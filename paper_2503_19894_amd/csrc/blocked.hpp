@@ -34,7 +34,19 @@ struct BlkGate {             // one fused gate inside a tile
     int8_t slot[32];         // block id -> index among the active blocks, -1: identity block
     uint64_t amask;          // diagonal: local indices whose phase is not 1
     uint64_t mat;            // offset (reals) of the gate's matrices in the fused list's buffer
+    uint32_t mat_reals;      // their size: 2 * 2^k (diagonal) or 2 * blocks * 4^d
+    uint32_t pad;
 };
+
+// LDS of a segment pass: the tile, then two gate areas (the gate being
+// applied and the next one, staged meanwhile).  An area holds the gate's
+// slot table (32 bytes), its iteration table (per loop iteration of the
+// workgroup, the wave-uniform part of the virtual coordinates or local index
+// and of the LDS address; at most 32 iterations), then its matrices.
+constexpr uint32_t kBlkIterOff = 64;
+constexpr uint32_t kBlkMaxIters = 32;
+constexpr uint32_t kBlkAreaHead = kBlkIterOff + kBlkMaxIters * 8;
+constexpr uint32_t kBlkMaxMatChunks = 512;    // 16-byte chunks of one gate's matrices (<= 2 per thread)
 
 struct BlkSeg {              // kernel arguments of one segment pass
     uint64_t ntiles;         // 2^(n - tb)
@@ -42,6 +54,7 @@ struct BlkSeg {              // kernel arguments of one segment pass
     int tb, w, nh;
     int qh[kBlkMaxHigh];     // high tile qubits, ascending
     uint32_t g0, g1;         // gates [g0, g1) of the gate table
+    uint32_t area;           // bytes of one gate area (head + the largest matrices of the segment)
 };
 
 }  // namespace cast

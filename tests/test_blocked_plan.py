@@ -70,6 +70,6 @@ def test_qft30_grouping_is_compact():
 
 def test_bad_tile_bits_rejected():
     with pytest.raises(cast.CastError):
-        cast.set_tuning("blocked_tile_bits", 14, torch.complex128)   # 256 KiB of LDS
+        cast.set_tuning("blocked_tile_bits", 13, torch.complex128)   # 128 KiB of LDS
     with pytest.raises(cast.CastError):
         cast.set_tuning("blocked_tile_bits", 7, torch.complex64)
