@@ -19,6 +19,9 @@ written once per pass).  The line also carries:
   vqa_grads_per_s -- batched adjoint VQA gradients/s (20 qubits, 320
                   parameters, 256 sets) against the plain per-instance
                   adjoint, both dtypes (details under extras.vqa);
+  blocked      -- the same fused QFT cache-blocked (several fused gates per
+                  HBM pass, apply_circuit_blocked): ms per step and HBM passes
+                  for both dtypes (details under extras.<dtype>.blocked);
   extras       -- the complex64 run and per-kernel breakdowns.
 """
 import argparse
@@ -112,9 +115,52 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
         "event_ms_per_step": float(per_pass.sum()),
         "kernels": kern, "dominant": dominant,
     }
+    out["blocked"] = run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, out["ms_per_step"])
     del sv, psi
     torch.cuda.empty_cache()
     return out
+
+
+def run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, per_pass_ms):
+    """The same fused circuit cache-blocked (several fused gates per HBM
+    pass): HBM passes, time per step, the passes' HBM rate (every pass reads
+    and writes the whole state once), and the largest amplitude difference
+    from the one-pass-per-gate path on the same input."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+
+    groups = fc.blocked_passes(dtype)
+    hbm = len(groups)
+    for _ in range(warmup):
+        sv.apply_circuit_blocked(fc)
+    torch.cuda.synchronize()
+    per = np.zeros(hbm)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per += sv.apply_circuit_blocked_timed(fc)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per /= steps
+    seg = [t for g, t in zip(groups, per) if g["tile_bits"]]
+    # same input through both paths
+    x = psi.clone()
+    sv_x = cast.StateVector(n, tensor=x)
+    sv_x.apply_circuit(fc)
+    y = psi.clone()
+    cast.StateVector(n, tensor=y).apply_circuit_blocked(fc)
+    torch.cuda.synchronize()
+    diff = float((x - y).abs().max())
+    del x, y, sv_x
+    torch.cuda.empty_cache()
+    ms = wall / steps * 1e3
+    return {
+        "hbm_passes": hbm, "segments": len(seg), "fused_gates_per_pass": [g["count"] for g in groups],
+        "ms_per_step": ms, "event_ms_per_step": float(per.sum()), "speedup_vs_per_pass": per_pass_ms / ms,
+        "hbm_gbs": hbm * 2 * state_bytes / (per.sum() * 1e-3) / 1e9,
+        "max_abs_diff_vs_per_pass": diff,
+    }
 
 
 def run_dense(n=32, depth=20, steps=1, warmup=1):
@@ -482,6 +528,9 @@ def main():
             "plain_c128": round(vqa["c128"]["plain"]["grads_per_s"], 2),
             "batched_c64": round(max(vqa["c64"]["graph"]["grads_per_s"], vqa["c64"]["persistent"]["grads_per_s"]), 2),
             "plain_c64": round(vqa["c64"]["plain"]["grads_per_s"], 2)},
+        "blocked": {d: {"ms_per_step": round(r["blocked"]["ms_per_step"], 3), "hbm_passes": r["blocked"]["hbm_passes"],
+                        "speedup_vs_per_pass": round(r["blocked"]["speedup_vs_per_pass"], 3)}
+                    for d, r in (("c128", main_run), ("c64", extras.get("c64"))) if r},
         "extras": {"c128": main_run, **extras, "vqa": vqa, "dense32": dense, "tfim_mixed": tfim},
     }
     print(json.dumps(line), flush=True)

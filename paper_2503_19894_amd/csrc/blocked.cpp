@@ -66,6 +66,8 @@ BlkGate make_gate(const PassPlan &p, int w, const int *qh, int nh, uint64_t mat)
     g.d = p.d;
     g.mat = mat;
     g.mat_reals = p.d == 0 ? 2u << p.k : (uint32_t)(2 * p.mat.size());
+    g.run = 1;
+    g.tshift = std::max(p.k, 1);
     for (int s = 0; s < p.k; ++s) {
         const int q = p.q[s];
         g.q[s] = q;
@@ -133,6 +135,11 @@ cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
     const int n = f.n;
     const std::vector<PassPlan> &P = f.plans;
     const std::vector<size_t> off = plan_offsets(P, dt);
+    // matrices / phase tables of one gate area: tile + two areas within the LDS budget
+    const size_t tile_bytes = ((size_t)1 << tb) * amp_bytes(dt);
+    const size_t area_max = std::min<size_t>(tile_bytes + 2 * kBlkAreaHead < kBlkLdsBudget
+                                                 ? (kBlkLdsBudget - tile_bytes) / 2 - kBlkAreaHead : 0,
+                                             (size_t)kBlkMaxMatChunks * 16);
     std::vector<size_t> cur;   // non-identity gates of the open segment
     size_t first = 0;
     uint64_t need = 0;
@@ -158,10 +165,37 @@ cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
             s.g0 = (uint32_t)bp->gates.size();
             for (size_t i : cur) bp->gates.push_back(make_gate(P[i], w, s.qh, s.nh, off[i]));
             s.g1 = (uint32_t)bp->gates.size();
+            // consecutive diagonal gates form runs applied in one sweep of the
+            // tile; a run's phase tables sit at the stride of its largest table
+            for (uint32_t gi = s.g0; gi < s.g1;) {
+                uint32_t m = 0;
+                int ts = 1;
+                while (gi + m < s.g1 && m < kBlkRunMax && bp->gates[gi + m].kind == 0) {
+                    const int ts2 = std::max(ts, bp->gates[gi + m].tshift);
+                    if (((size_t)(m + 1) << ts2) * amp_bytes(dt) > area_max && m > 0) break;
+                    ts = ts2;
+                    ++m;
+                }
+                if (m == 0) {
+                    ++gi;
+                    continue;
+                }
+                bp->gates[gi].run = (int)m;
+                bp->gates[gi].tshift = ts;
+                for (uint32_t j = 1; j < m; ++j) bp->gates[gi + j].run = 0;
+                gi += m;
+            }
             uint32_t mbytes = 0;
-            for (uint32_t gi = s.g0; gi < s.g1; ++gi)
-                mbytes = std::max<uint32_t>(mbytes, bp->gates[gi].mat_reals * (dt == CAST_C128 ? 8 : 4));
+            for (uint32_t gi = s.g0; gi < s.g1; ++gi) {
+                const BlkGate &g = bp->gates[gi];
+                if (g.kind == 0 && g.run == 0) continue;
+                const uint32_t b = g.kind == 0 ? ((uint32_t)g.run << g.tshift) * (uint32_t)amp_bytes(dt)
+                                               : g.mat_reals * (dt == CAST_C128 ? 8 : 4);
+                mbytes = std::max(mbytes, b);
+            }
             s.area = kBlkAreaHead + ((mbytes + 15) & ~15u);
+            s.maxd = 0;
+            for (uint32_t gi = s.g0; gi < s.g1; ++gi) s.maxd = std::max(s.maxd, bp->gates[gi].d);
             bp->passes.push_back(ps);
         }
         cur.clear();
@@ -173,8 +207,9 @@ cast_status build(const cast_fused &f, cast_dtype dt, BlockedPlan **out) {
         if (p.identity()) continue;
         const uint64_t sp = span_qubits(p);
         int w;
-        const size_t mchunks = ((p.d == 0 ? (2u << p.k) : 2 * p.mat.size()) * amp_bytes(dt) / 2 + 15) / 16;
-        if (n < tb || p.d > kBlkMaxD || mchunks > kBlkMaxMatChunks || !window_of(sp, tb, &w)) {
+        const size_t mbytes = (p.d == 0 ? ((size_t)2 << std::max(p.k, 1)) : 2 * p.mat.size()) * amp_bytes(dt) / 2;
+        if (n < tb || p.d > kBlkMaxD || (mbytes + 15) / 16 > kBlkMaxMatChunks || mbytes > area_max ||
+            !window_of(sp, tb, &w)) {
             // an ordinary pass of its own
             close(i);
             BlockedPlan::Pass ps;

@@ -68,76 +68,115 @@ __device__ __forceinline__ uint32_t iters_of(const BlkGate &g, uint32_t tile_amp
     return (items + NT - 1) / NT;
 }
 
-// Staging of a gate area in two halves: the matrices are read from global
-// memory into registers before the current gate is applied (so their
-// latency hides behind it) and written to LDS afterwards, together with the
-// slot table and the iteration table of this tile.
+// Staging of a gate area in two halves: the matrices (or a diagonal run's
+// phase tables) are read from global memory into registers before the
+// current gate is applied, so their latency hides behind it, and written to
+// LDS afterwards, together with the slot table and this tile's iteration
+// tables.
 struct Prefetch {
     u4 m[kBlkMaxMatChunks / 256];
 };
 
 template <typename R, int NT>
-__device__ __forceinline__ void prefetch(Prefetch &pf, const R *mats, const BlkGate &g) {
-    const u4 *src = reinterpret_cast<const u4 *>(mats + g.mat);   // 256-byte aligned
-    const uint32_t n16 = (g.mat_reals * (uint32_t)sizeof(R) + 15) / 16;
+__device__ __forceinline__ void prefetch(Prefetch &pf, const R *mats, const BlkGate *gates, uint32_t gi) {
+    const BlkGate &g = gates[gi];
+    // 16-byte chunks per phase-table stride: 2^tshift entries of 2 reals
+    const uint32_t cshift = g.tshift + (sizeof(R) == 8 ? 0 : -1);
 #pragma unroll
     for (int r = 0; r < (int)((kBlkMaxMatChunks + NT - 1) / NT); ++r) {
         const uint32_t i = threadIdx.x + r * NT;
-        if (i < n16) pf.m[r] = src[i];
+        if (g.kind == 0) {
+            const uint32_t t = i >> cshift, o = i & ((1u << cshift) - 1);
+            if (t < (uint32_t)g.run) {
+                const BlkGate &h = gates[gi + t];
+                if (o < (h.mat_reals * (uint32_t)sizeof(R) + 15) / 16)
+                    pf.m[r] = reinterpret_cast<const u4 *>(mats + h.mat)[o];
+            }
+        } else if (i < (g.mat_reals * (uint32_t)sizeof(R) + 15) / 16) {
+            pf.m[r] = reinterpret_cast<const u4 *>(mats + g.mat)[i];   // 256-byte aligned
+        }
     }
 }
 
 template <typename R, int S, int NT>
-__device__ __forceinline__ void commit(char *area, const Prefetch &pf, const BlkGate &g, uint64_t tbase,
-                                       uint32_t tile_amps) {
-    if (threadIdx.x < 32) reinterpret_cast<int8_t *>(area)[threadIdx.x] = g.slot[threadIdx.x];
+__device__ __forceinline__ void commit(char *area, const Prefetch &pf, const BlkGate *gates, uint32_t gi,
+                                       uint64_t tbase, uint32_t tile_amps) {
+    const BlkGate &g = gates[gi];
     u4 *dst = reinterpret_cast<u4 *>(area + kBlkAreaHead);
+    uint2 *itab = reinterpret_cast<uint2 *>(area + kBlkIterOff);
+    if (g.kind == 0) {
+        const uint32_t cshift = g.tshift + (sizeof(R) == 8 ? 0 : -1);
+#pragma unroll
+        for (int r = 0; r < (int)((kBlkMaxMatChunks + NT - 1) / NT); ++r) {
+            const uint32_t i = threadIdx.x + r * NT;
+            const uint32_t t = i >> cshift, o = i & ((1u << cshift) - 1);
+            if (t < (uint32_t)g.run && o < (gates[gi + t].mat_reals * (uint32_t)sizeof(R) + 15) / 16)
+                dst[i] = pf.m[r];
+        }
+        // per (gate t of the run, iteration i): uniform part of its local index
+        const uint32_t iters = tile_amps / NT;
+        if (threadIdx.x < (uint32_t)g.run * iters) {
+            const uint32_t t = threadIdx.x / iters, i = threadIdx.x % iters;
+            const BlkGate &h = gates[gi + t];
+            uint32_t juni = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                if (q < h.k && h.tpos[q] < 0 && ((tbase >> h.q[q]) & 1u)) juni |= 1u << q;
+            reinterpret_cast<uint32_t *>(area + kBlkJOff)[t * kBlkMaxIters + i] = juni ^ loc(i * NT, h);
+            if (t == 0) itab[i] = make_uint2(0u, at<S>(i * NT));
+        }
+        return;
+    }
+    if (threadIdx.x < 32) reinterpret_cast<int8_t *>(area)[threadIdx.x] = g.slot[threadIdx.x];
     const uint32_t n16 = (g.mat_reals * (uint32_t)sizeof(R) + 15) / 16;
 #pragma unroll
     for (int r = 0; r < (int)((kBlkMaxMatChunks + NT - 1) / NT); ++r) {
         const uint32_t i = threadIdx.x + r * NT;
         if (i < n16) dst[i] = pf.m[r];
     }
-    // iteration i covers items i*NT + lane; its uniform part is item i*NT
-    if (threadIdx.x < iters_of<NT>(g, tile_amps)) {
-        uint32_t juni = 0, uuni = 0;   // targets outside the tile, fixed by the tile
+    // iteration i covers cosets i*NT + lane; its uniform part is coset i*NT
+    const uint32_t items = tile_amps >> g.d;
+    if (threadIdx.x < (items + NT - 1) / NT) {
+        uint32_t uuni = 0;   // targets outside the tile, fixed by the tile
 #pragma unroll
         for (int q = 0; q < 6; ++q)
-            if (q < g.k && g.tpos[q] < 0 && ((tbase >> g.q[q]) & 1u)) juni |= 1u << q, uuni ^= g.colv[q];
-        const uint32_t i0 = threadIdx.x * NT;
-        uint2 e;
-        if (g.kind == 0) {
-            e.x = juni ^ loc(i0, g);
-            e.y = at<S>(i0);
-        } else {
-            uint32_t y = i0;
-            for (int i = 0; i < g.d; ++i) y = ((y & ~g.pivlow[i]) << 1) | (y & g.pivlow[i]);
-            e.x = uuni ^ virt(y, g);
-            e.y = at<S>(y);
-        }
-        reinterpret_cast<uint2 *>(area + kBlkIterOff)[threadIdx.x] = e;
+            if (q < g.k && g.tpos[q] < 0 && ((tbase >> g.q[q]) & 1u)) uuni ^= g.colv[q];
+        uint32_t y = threadIdx.x * NT;
+        for (int i = 0; i < g.d; ++i) y = ((y & ~g.pivlow[i]) << 1) | (y & g.pivlow[i]);
+        itab[threadIdx.x] = make_uint2(uuni ^ virt(y, g), at<S>(y));
     }
 }
 
-// Diagonal gate: amplitude y gets phase D[j(y)], j = its bits at the targets.
-// Identity phases are exactly 1, so every amplitude is simply multiplied.
+// A run of m diagonal gates: amplitude y is read once, multiplied by each
+// gate's phase D_t[j_t(y)] in order (identity phases are exactly 1), and
+// written once.
 template <typename R, int S, int NT>
-__device__ __forceinline__ void diag_in_tile(typename Cx<R>::T *tile, const char *area, const BlkGate &g,
-                                             uint32_t tile_amps) {
+__device__ __forceinline__ void diag_run(typename Cx<R>::T *tile, const char *area, const BlkGate *gates,
+                                         uint32_t gi, uint32_t tile_amps) {
     using V = typename Cx<R>::T;
-    const V *tab = reinterpret_cast<const V *>(area + kBlkAreaHead);
+    const int m = gates[gi].run;
+    const int ts = gates[gi].tshift;
+    const V *tabs = reinterpret_cast<const V *>(area + kBlkAreaHead);
     const uint2 *itab = reinterpret_cast<const uint2 *>(area + kBlkIterOff);
-    const uint32_t jl = loc(threadIdx.x, g);
+    const uint32_t *jt = reinterpret_cast<const uint32_t *>(area + kBlkJOff);
+    uint32_t jl[kBlkRunMax];
+#pragma unroll
+    for (int t = 0; t < (int)kBlkRunMax; ++t) jl[t] = t < m ? loc(threadIdx.x, gates[gi + t]) : 0u;
     const uint32_t al = at<S>(threadIdx.x);
     const uint32_t iters = tile_amps / NT;
     for (uint32_t i = 0; i < iters; ++i) {
-        const uint2 e = itab[i];
-        V &a = tile[al ^ e.y];
-        const V t = tab[jl ^ e.x];
-        const R re = a.x * t.x - a.y * t.y;
-        const R im = a.x * t.y + a.y * t.x;
-        a.x = re;
-        a.y = im;
+        const uint32_t a = al ^ itab[i].y;
+        V x = tile[a];
+#pragma unroll
+        for (int t = 0; t < (int)kBlkRunMax; ++t) {
+            if (t >= m) break;
+            const V ph = tabs[(t << ts) + (jl[t] ^ jt[t * kBlkMaxIters + i])];
+            const R re = x.x * ph.x - x.y * ph.y;
+            const R im = x.x * ph.y + x.y * ph.x;
+            x.x = re;
+            x.y = im;
+        }
+        tile[a] = x;
     }
 }
 
@@ -204,8 +243,12 @@ __device__ __forceinline__ void block_in_tile(typename Cx<R>::T *tile, const cha
     }
 }
 
-template <typename R, int NT>
-__global__ void __launch_bounds__(NT) k_blocked(R *__restrict__ psi_r, const R *__restrict__ mats,
+// MAXD: the largest block dimension the instance handles (segments without
+// 8 x 8 blocks use the MAXD = 2 instance, which needs fewer registers; the
+// MAXD = 3 instance is held to 128 registers, four waves per SIMD, so that
+// two workgroups still share a compute unit).
+template <typename R, int NT, int MAXD>
+__global__ void __launch_bounds__(NT, MAXD >= 3 ? 4 : 1) k_blocked(R *__restrict__ psi_r, const R *__restrict__ mats,
                                                 const BlkGate *__restrict__ gates, BlkSeg s) {
     using V = typename Cx<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;
@@ -236,27 +279,33 @@ __global__ void __launch_bounds__(NT) k_blocked(R *__restrict__ psi_r, const R *
             }
         }
         Prefetch pf;
-        prefetch<R, NT>(pf, mats, gates[s.g0]);
-        commit<R, S, NT>(area0, pf, gates[s.g0], tbase, tile_amps);
+        prefetch<R, NT>(pf, mats, gates, s.g0);
+        commit<R, S, NT>(area0, pf, gates, s.g0, tbase, tile_amps);
         __syncthreads();
-        // ---- the segment's gates, in order; the next gate is staged into
-        // the other area meanwhile
-        for (uint32_t gi = s.g0; gi < s.g1; ++gi) {
+        // ---- the segment's gates (a diagonal run counts as one), in order;
+        // the next one is staged into the other area meanwhile
+        uint32_t par = 0;
+        for (uint32_t gi = s.g0; gi < s.g1;) {
             const BlkGate &g = gates[gi];
-            char *area = area0 + ((gi - s.g0) & 1u) * s.area;
-            const bool more = gi + 1 < s.g1;
-            if (more) prefetch<R, NT>(pf, mats, gates[gi + 1]);
+            const uint32_t gn = gi + (g.kind == 0 ? (uint32_t)g.run : 1u);
+            char *area = area0 + par * s.area;
+            const bool more = gn < s.g1;
+            if (more) prefetch<R, NT>(pf, mats, gates, gn);
             if (g.kind == 0) {
-                diag_in_tile<R, S, NT>(tile, area, g, tile_amps);
+                diag_run<R, S, NT>(tile, area, gates, gi, tile_amps);
             } else {
                 switch (g.d) {
                     case 1: block_in_tile<1, R, S, NT>(tile, area, g, tile_amps); break;
                     case 2: block_in_tile<2, R, S, NT>(tile, area, g, tile_amps); break;
-                    default: block_in_tile<3, R, S, NT>(tile, area, g, tile_amps); break;
+                    default:
+                        if (MAXD >= 3) block_in_tile<3, R, S, NT>(tile, area, g, tile_amps);
+                        break;
                 }
             }
-            if (more) commit<R, S, NT>(area0 + ((gi + 1 - s.g0) & 1u) * s.area, pf, gates[gi + 1], tbase, tile_amps);
+            if (more) commit<R, S, NT>(area0 + (par ^ 1u) * s.area, pf, gates, gn, tbase, tile_amps);
             __syncthreads();
+            gi = gn;
+            par ^= 1u;
         }
         // ---- store
         for (uint32_t c0 = 0; c0 < chunks; c0 += B * NT) {
@@ -271,30 +320,31 @@ __global__ void __launch_bounds__(NT) k_blocked(R *__restrict__ psi_r, const R *
     }
 }
 
-template <typename R, int NT>
-hipError_t allow_lds() {
-    static hipError_t done = hipFuncSetAttribute((const void *)k_blocked<R, NT>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10);
-    return done;
-}
-
-template <typename R, int NT>
+template <typename R, int NT, int MAXD>
 hipError_t launch_nt(R *psi, const R *mats, const BlkGate *gates, const BlkSeg &s, uint32_t grid, size_t lds,
                      hipStream_t stream) {
-    const hipError_t ae = allow_lds<R, NT>();
-    if (ae != hipSuccess) return ae;
-    hipLaunchKernelGGL((k_blocked<R, NT>), dim3(grid), dim3(NT), lds, stream, psi, mats, gates, s);
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_blocked<R, NT, MAXD>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_blocked<R, NT, MAXD>), dim3(grid), dim3(NT), lds, stream, psi, mats, gates, s);
     return hipGetLastError();
+}
+
+template <typename R, int MAXD>
+hipError_t launch_d(int nt, R *psi, const R *mats, const BlkGate *gates, const BlkSeg &s, uint32_t grid,
+                    size_t lds, hipStream_t stream) {
+    switch (nt) {
+        case 256: return launch_nt<R, 256, MAXD>(psi, mats, gates, s, grid, lds, stream);
+        case 512: return launch_nt<R, 512, MAXD>(psi, mats, gates, s, grid, lds, stream);
+        default: return launch_nt<R, 1024, MAXD>(psi, mats, gates, s, grid, lds, stream);
+    }
 }
 
 template <typename R>
 hipError_t launch_r(int nt, R *psi, const R *mats, const BlkGate *gates, const BlkSeg &s, uint32_t grid,
                     size_t lds, hipStream_t stream) {
-    switch (nt) {
-        case 256: return launch_nt<R, 256>(psi, mats, gates, s, grid, lds, stream);
-        case 512: return launch_nt<R, 512>(psi, mats, gates, s, grid, lds, stream);
-        default: return launch_nt<R, 1024>(psi, mats, gates, s, grid, lds, stream);
-    }
+    if (s.maxd >= 3) return launch_d<R, 3>(nt, psi, mats, gates, s, grid, lds, stream);
+    return launch_d<R, 2>(nt, psi, mats, gates, s, grid, lds, stream);
 }
 
 }  // namespace

@@ -35,18 +35,27 @@ struct BlkGate {             // one fused gate inside a tile
     uint64_t amask;          // diagonal: local indices whose phase is not 1
     uint64_t mat;            // offset (reals) of the gate's matrices in the fused list's buffer
     uint32_t mat_reals;      // their size: 2 * 2^k (diagonal) or 2 * blocks * 4^d
-    uint32_t pad;
+    int run;                 // diagonal: gates applied together from here (a run), 0 inside a run
+    int tshift;              // first gate of a run: log2 of its phase-table stride (entries)
+    int pad;
 };
 
-// LDS of a segment pass: the tile, then two gate areas (the gate being
-// applied and the next one, staged meanwhile).  An area holds the gate's
-// slot table (32 bytes), its iteration table (per loop iteration of the
-// workgroup, the wave-uniform part of the virtual coordinates or local index
-// and of the LDS address; at most 32 iterations), then its matrices.
+// LDS of a segment pass: the tile, then two gate areas (the gate or run of
+// diagonal gates being applied and the next one, staged meanwhile).  An area
+// holds the slot table (32 bytes); the iteration table (per loop iteration
+// of the workgroup, the wave-uniform part of the virtual coordinates and of
+// the LDS address; at most 32 iterations); for a run of diagonal gates the
+// uniform part of each gate's local index per iteration; then the matrices,
+// or the run's phase tables at a stride of 2^tshift entries.  The planner
+// keeps tile + two areas within kBlkLdsBudget, so two workgroups share a
+// compute unit's 160 KiB of LDS.
 constexpr uint32_t kBlkIterOff = 64;
 constexpr uint32_t kBlkMaxIters = 32;
-constexpr uint32_t kBlkAreaHead = kBlkIterOff + kBlkMaxIters * 8;
+constexpr uint32_t kBlkRunMax = 8;
+constexpr uint32_t kBlkJOff = kBlkIterOff + kBlkMaxIters * 8;
+constexpr uint32_t kBlkAreaHead = kBlkJOff + kBlkRunMax * kBlkMaxIters * 4;
 constexpr uint32_t kBlkMaxMatChunks = 512;    // 16-byte chunks of one gate's matrices (<= 2 per thread)
+constexpr uint32_t kBlkLdsBudget = 80u << 10;
 
 struct BlkSeg {              // kernel arguments of one segment pass
     uint64_t ntiles;         // 2^(n - tb)
@@ -55,6 +64,7 @@ struct BlkSeg {              // kernel arguments of one segment pass
     int qh[kBlkMaxHigh];     // high tile qubits, ascending
     uint32_t g0, g1;         // gates [g0, g1) of the gate table
     uint32_t area;           // bytes of one gate area (head + the largest matrices of the segment)
+    int maxd;                // largest block dimension among the segment's gates (selects the kernel)
 };
 
 }  // namespace cast
