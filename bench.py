@@ -358,9 +358,9 @@ KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_
                              "apply.hip")
 
 
-def source_digest():
+def source_digest(path=None):
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(open(path or KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
 
 
 def recorded_traffic(kernel):
@@ -379,11 +379,18 @@ def recorded_traffic(kernel):
     return None
 
 
-def summarize_kernel_trace(stats_csv, command):
+def summarize_kernel_trace(stats_csv, command, name_filter=None):
+    """Top kernels of a rocprofv3 --stats CSV; with name_filter, only kernels
+    whose name contains it (the digest is then that of blocked.hip for the
+    cache-blocked kernel, else of apply.hip)."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
-    out = [f"# rocprofv3 kernel-trace summary", f"# command: {command}",
-           f"# kernel_source_sha256_16: {source_digest()}",
+    if name_filter:
+        rows = [r for r in rows if name_filter in r["Name"]]
+    src = os.path.join(os.path.dirname(KERNEL_SOURCE), "blocked.hip") if name_filter == "k_blocked" else None
+    out = [f"# rocprofv3 kernel-trace summary" + (f" (kernels matching {name_filter})" if name_filter else ""),
+           f"# command: {command}",
+           f"# kernel_source_sha256_16: {source_digest(src)}",
            f"{'kernel':78s} {'calls':>6s} {'avg_ms':>9s} {'total_ms':>10s} {'min_ms':>8s} {'max_ms':>8s} {'pct':>6s}"]
     for r in rows[:14]:
         out.append(f"{r['Name'][:78]:78s} {int(r['Calls']):6d} {float(r['AverageNs'])/1e6:9.4f} "
@@ -448,7 +455,7 @@ def main():
     ap.add_argument("--dense-only", action="store_true", help="only the 32-qubit dense circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
-    ap.add_argument("--summarize-kernel-trace", nargs=2, metavar=("STATS_CSV", "COMMAND"))
+    ap.add_argument("--summarize-kernel-trace", nargs="+", metavar="STATS_CSV COMMAND [NAME_FILTER]")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
     args = ap.parse_args()
     if args.summarize_kernel_trace:
