@@ -121,6 +121,49 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     return out
 
 
+def run_families(n=30, dtype_names=("c128", "c64")):
+    """Synthetic stand-ins of the paper's circuit families (QFT, IQP, ALA,
+    QVC, RQC, HES) on n qubits from a random state: for each fusion setting
+    (none = k_max 1, size-only k_max 5, adaptive k_max 5 with the measured
+    cost table) the fused-gate count, host fusion time, one-pass-per-gate time
+    and cache-blocked time (one warm-up application each, then one timed)."""
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import FAMILIES, random_state_torch
+
+    modes = {"none": dict(k_max=1), "size": dict(k_max=5), "adaptive": dict(k_max=5, cost_model=1)}
+    out = {}
+    for dname in dtype_names:
+        dtype = torch.complex128 if dname == "c128" else torch.complex64
+        psi = random_state_torch(n, seed=0, device="cuda", dtype=dtype)
+        sv = cast.StateVector(n, tensor=psi)
+        res = {}
+        for fam, mk in FAMILIES.items():
+            gates = mk(n)
+            res[fam] = {"gates": len(gates)}
+            for mode, opts in modes.items():
+                print(f"[bench] families {dname} {fam} {mode}", file=sys.stderr, flush=True)
+                t0 = time.perf_counter()
+                fc = cast.FusedCircuit(n, gates, cost_dtype=dtype, **opts)
+                fus = (time.perf_counter() - t0) * 1e3
+                row = {"fused": len(fc), "host_fusion_ms": round(fus, 2)}
+                for path, apply in (("per_pass", sv.apply_circuit), ("blocked", sv.apply_circuit_blocked)):
+                    apply(fc)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    apply(fc)
+                    torch.cuda.synchronize()
+                    row[path + "_s"] = round(time.perf_counter() - t0, 4)
+                row["hbm_passes_blocked"] = len(fc.blocked_passes(dtype))
+                res[fam][mode] = row
+                del fc
+        out[dname] = res
+        del sv, psi
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, per_pass_ms):
     """The same fused circuit cache-blocked (several fused gates per HBM
     pass): HBM passes, time per step, the passes' HBM rate (every pass reads
@@ -456,6 +499,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-kernel-trace", nargs="+", metavar="STATS_CSV COMMAND [NAME_FILTER]")
+    ap.add_argument("--families", action="store_true",
+                    help="only the circuit-family table (fusion none / size-only / adaptive, per pass and "
+                         "cache-blocked); prints one JSON object")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
     args = ap.parse_args()
     if args.summarize_kernel_trace:
@@ -481,6 +527,9 @@ def main():
         return
     if args.vqa_only:
         print(json.dumps(run_vqa(oracle_check=False)), flush=True)
+        return
+    if args.families:
+        print(json.dumps(run_families(args.n)), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

@@ -213,3 +213,66 @@ def gate_sweep(kind: str, k: int, targets: Sequence[int], seed: int = 0) -> List
         m[np.ix_([c, c | hi], [c, c | hi])] = u
         return [Gate("unitary", t, matrix=m)]
     raise ValueError(kind)
+
+
+# ----------------------------------------------------------- benchmark families
+# Synthetic stand-ins for the paper's circuit families (Sec. V; the circuit
+# files themselves are not available): seeded, with the families' gate mix.
+
+def iqp(n: int, seed: int = 0, density: float = 0.3) -> List[Gate]:
+    """IQP: H on every qubit, a diagonal layer (RZ on every qubit and CP with
+    random angles on a random subset of all pairs), H on every qubit."""
+    rng = _rng(11, seed)
+    gates = [Gate("h", (q,)) for q in range(n)]
+    gates += [Gate("rz", (q,), (float(rng.uniform(0, 2 * math.pi)),)) for q in range(n)]
+    for i in range(n):
+        for j in range(i + 1, n):
+            if rng.random() < density:
+                gates.append(Gate("cp", (i, j), (float(rng.uniform(0, 2 * math.pi)),)))
+    gates += [Gate("h", (q,)) for q in range(n)]
+    return gates
+
+
+def ala(n: int, layers: int = 10, seed: int = 0) -> List[Gate]:
+    """Alternating layered ansatz: per layer RY on every qubit, then CZ on the
+    brick pairs (i, i+1) starting at 0 on even and 1 on odd layers."""
+    rng = _rng(12, seed)
+    gates: List[Gate] = []
+    for layer in range(layers):
+        gates += [Gate("ry", (q,), (float(rng.uniform(0, 2 * math.pi)),)) for q in range(n)]
+        gates += [Gate("cz", (c, c + 1)) for c in range(layer % 2, n - 1, 2)]
+    return gates
+
+
+def qvc(n: int, depth: int = 10, seed: int = 0) -> List[Gate]:
+    """Quantum-volume circuit: per layer a random pairing of the qubits, a
+    Haar-random two-qubit unitary on each pair."""
+    rng = _rng(13, seed)
+    gates: List[Gate] = []
+    for _ in range(depth):
+        perm = rng.permutation(n)
+        for i in range(0, n - 1, 2):
+            gates.append(Gate("unitary", (int(perm[i]), int(perm[i + 1])), matrix=haar_unitary(4, rng)))
+    return gates
+
+
+def hes(n: int, steps: int = 10, dt: float = 0.05, seed: int = 0) -> List[Gate]:
+    """Hamiltonian simulation: Strang-Trotter steps of a transverse-field Ising
+    ring (RZ field half-steps with random fields, RXX couplings), fixed angles."""
+    h = _rng(14, seed).uniform(0.5, 1.5, n)
+    gates: List[Gate] = []
+    for _ in range(steps):
+        gates += [Gate("rz", (i,), (float(-h[i] * dt),)) for i in range(n)]
+        gates += [Gate("rxx", (i, (i + 1) % n), (-2.0 * dt,)) for i in range(n)]
+        gates += [Gate("rz", (i,), (float(-h[i] * dt),)) for i in range(n)]
+    return gates
+
+
+FAMILIES = {
+    "qft": lambda n: qft(n),
+    "iqp": lambda n: iqp(n),
+    "ala": lambda n: ala(n),
+    "qvc": lambda n: qvc(n),
+    "rqc": lambda n: rqc_u3_cx(n, 10, seed=0),
+    "hes": lambda n: hes(n),
+}
