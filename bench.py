@@ -54,10 +54,11 @@ def kernel_label(info, dtype_name):
             ipt >>= 1
         nt = "true" if cast.get_tuning("direct_nt", dt) else "false"
         return f"k_direct<{d}, {r}, {ipt}, {nt}>"
+    m3 = "true" if d >= cast.get_tuning("mfma_3m_min_d", dt) else "false"
     if kind == 4:
-        return f"k_mfma_direct<{d}, {r}>"
+        return f"k_mfma_direct<{d}, {r}, {m3}>"
     if kind == 5:
-        return f"k_mfma_tile<{d}, {r}>"
+        return f"k_mfma_tile<{d}, {r}, {m3}>"
     two = "true" if kind == 2 else "false"
     return f"k_tile<{d}, {r}, true, {two}>"
 
@@ -476,7 +477,7 @@ def summarize_traffic(fetch_csv, write_csv, command_fetch, command_write):
         if not fv or not wv:
             continue
         fa, wa = sum(fv) / len(fv), sum(wv) / len(wv)
-        label = name.split("(")[0].replace("void cast::", "")
+        label = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void cast::", "")
         out.append(f"{label} | {len(fv)} | {fa:.1f} | {wa:.1f} | {(fa * ff + wa * wf) * 1024:.0f}")
     return "\n".join(out)
 

@@ -227,7 +227,9 @@ void fused_destroy(cast_fused *f);
  * pattern-major 1), "blocked_tile_bits" (log2 amplitudes per tile of the
  * cache-blocked passes, 8..12 for complex128, 8..13 for complex64: tiles of
  * at most 64 KiB, so two workgroups share a compute unit's LDS),
- * "blocked_threads" (their workgroup size: 256, 512 or 1024).
+ * "blocked_threads" (their workgroup size: 256, 512 or 1024),
+ * "mfma_3m_min_d" (matrix-core passes with blocks of d >= this value form
+ * complex products with three real products instead of four; 4..7, 7 = never).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

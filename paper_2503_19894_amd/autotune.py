@@ -39,6 +39,7 @@ KNOB_CHOICES = [
     ("diag_max_grid", [1 << 14, 1 << 16, 1 << 18, 1 << 20]),
     ("diag_lds_table", [0, 1]),
     ("diag_order", [0, 1]),
+    ("mfma_3m_min_d", [4, 5, 6, 7]),
 ]
 
 

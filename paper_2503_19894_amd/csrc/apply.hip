@@ -477,30 +477,49 @@ __device__ __forceinline__ void stage_blocks(V *mt, const R *mat, uint32_t nblk)
 
 // One unit: 16 groups of block slot bs.  load(c) returns X[c][group lane%16]
 // (this lane's k-row c); store(row, value) writes Y[row][group lane%16].
-template <int D, typename R, typename Load, typename Store>
+// M3 = false: four real products per k-step, Yr += Ur Xr - Ui Xi and
+// Yi += Ur Xi + Ui Xr.  M3 = true: the three-multiplication form of the
+// complex product (Gauss; the "3M method" for complex matrix products):
+// P = Ur Xr, Q = Ui Xi, S = (Ur + Ui)(Xr + Xi), then Yr = P - Q and
+// Yi = S - P - Q, one matrix-core product fewer per k-step.
+template <int D, typename R, bool M3, typename Load, typename Store>
 __device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load load, Store store) {
     using V = typename Amp<R>::T;
     using M = Mfma<R>;
     constexpr int N = 1 << D, T = N / 16;
     const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
-    typename M::acc cr[T], ci[T];
+    typename M::acc cr[T], ci[T], cs[M3 ? T : 1];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) cr[t][v] = ci[t][v] = 0;
+        for (int v = 0; v < 4; ++v) {
+            cr[t][v] = ci[t][v] = 0;
+            if (M3) cs[t][v] = 0;
+        }
     }
 #pragma unroll 4
     for (int s = 0; s < N / 4; ++s) {
         const int c = 4 * s + kk;
         const V x = load(c);
         const V *col = mt_blk + c * N + j;
+        if (M3) {
+            const R xs = x.x + x.y;
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const V u = col[16 * t];
-            cr[t] = M::mma(u.x, x.x, cr[t]);
-            cr[t] = M::mma(-u.y, x.y, cr[t]);
-            ci[t] = M::mma(u.x, x.y, ci[t]);
-            ci[t] = M::mma(u.y, x.x, ci[t]);
+            for (int t = 0; t < T; ++t) {
+                const V u = col[16 * t];
+                cr[t] = M::mma(u.x, x.x, cr[t]);
+                ci[t] = M::mma(u.y, x.y, ci[t]);
+                cs[t] = M::mma(u.x + u.y, xs, cs[t]);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const V u = col[16 * t];
+                cr[t] = M::mma(u.x, x.x, cr[t]);
+                cr[t] = M::mma(-u.y, x.y, cr[t]);
+                ci[t] = M::mma(u.x, x.y, ci[t]);
+                ci[t] = M::mma(u.y, x.x, ci[t]);
+            }
         }
     }
 #pragma unroll
@@ -508,8 +527,13 @@ __device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             V y;
-            y.x = cr[t][v];
-            y.y = ci[t][v];
+            if (M3) {
+                y.x = cr[t][v] - ci[t][v];
+                y.y = cs[t][v] - cr[t][v] - ci[t][v];
+            } else {
+                y.x = cr[t][v];
+                y.y = ci[t][v];
+            }
             store(16 * t + M::row(lane, v), y);
         }
     }
@@ -524,7 +548,7 @@ __device__ __forceinline__ uint64_t off_of(const uint64_t *off, int c) {
     return o;
 }
 
-template <int D, typename R>
+template <int D, typename R, bool M3>
 __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, const R *__restrict__ mat, PassArgs a) {
     using V = typename Amp<R>::T;
     constexpr int N = 1 << D;
@@ -543,13 +567,13 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
         uint64_t base = deposit(g, a.lowmask, a.k);
         for (int q = 0; q < a.k - D; ++q)
             if ((bid >> q) & 1u) base ^= a.off[D + q];
-        mfma_unit<D, R>(
+        mfma_unit<D, R, M3>(
             mt + (size_t)bs * N * N, [&](int c) { return psi[base ^ off_of<D>(a.off, c)]; },
             [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; });
     }
 }
 
-template <int D, typename R>
+template <int D, typename R, bool M3>
 __global__ void __launch_bounds__(256) k_mfma_tile(R *__restrict__ psi_r, const R *__restrict__ mat, PassArgs a) {
     using V = typename Amp<R>::T;
     constexpr int N = 1 << D;
@@ -597,7 +621,7 @@ __global__ void __launch_bounds__(256) k_mfma_tile(R *__restrict__ psi_r, const 
                     if ((c >> b) & 1) o ^= a.toff[b];
                 return o;
             };
-            mfma_unit<D, R>(
+            mfma_unit<D, R, M3>(
                 mt + (size_t)bs * N * N, [&](int c) { return tile[lds_elem<S>(pos ^ toff_of(c))]; },
                 [&](int row, const V &y) { tile[lds_elem<S>(pos ^ toff_of(row))] = y; });
         }
@@ -746,34 +770,32 @@ bool mfma_fits(int n, cast_dtype dt, const PassPlan &p) {
 }
 
 template <typename R>
-static hipError_t launch_mfma(int D, bool tile, R *psi, const R *m, const PassArgs &a, int grid, size_t lds,
-                              hipStream_t s) {
+static hipError_t launch_mfma(int D, bool tile, bool m3, R *psi, const R *m, const PassArgs &a, int grid,
+                              size_t lds, hipStream_t s) {
+#define CAST_MFMA_K(KERN, DD, M3)                                                                        \
+    {                                                                                                    \
+        static bool set = false;                                                                         \
+        if (!set) {                                                                                      \
+            hipError_t e = hipFuncSetAttribute((const void *)KERN<DD, R, M3>,                            \
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10);   \
+            if (e != hipSuccess) return e;                                                               \
+            set = true;                                                                                  \
+        }                                                                                                \
+        hipLaunchKernelGGL((KERN<DD, R, M3>), dim3(grid), dim3(256), lds, s, psi, m, a);                 \
+    }
 #define CAST_MFMA(DD)                                                                                    \
     case DD:                                                                                             \
         if (tile) {                                                                                      \
-            static bool set = false;                                                                     \
-            if (!set) {                                                                                  \
-                hipError_t e = hipFuncSetAttribute((const void *)k_mfma_tile<DD, R>,                     \
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10); \
-                if (e != hipSuccess) return e;                                                           \
-                set = true;                                                                              \
-            }                                                                                            \
-            hipLaunchKernelGGL((k_mfma_tile<DD, R>), dim3(grid), dim3(256), lds, s, psi, m, a);          \
+            if (m3) CAST_MFMA_K(k_mfma_tile, DD, true) else CAST_MFMA_K(k_mfma_tile, DD, false)         \
         } else {                                                                                         \
-            static bool set = false;                                                                     \
-            if (!set) {                                                                                  \
-                hipError_t e = hipFuncSetAttribute((const void *)k_mfma_direct<DD, R>,                   \
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10); \
-                if (e != hipSuccess) return e;                                                           \
-                set = true;                                                                              \
-            }                                                                                            \
-            hipLaunchKernelGGL((k_mfma_direct<DD, R>), dim3(grid), dim3(256), lds, s, psi, m, a);        \
+            if (m3) CAST_MFMA_K(k_mfma_direct, DD, true) else CAST_MFMA_K(k_mfma_direct, DD, false)     \
         }                                                                                                \
         break;
     switch (D) {
         CAST_MFMA(4) CAST_MFMA(5) CAST_MFMA(6)
         default: return hipErrorInvalidValue;
     }
+#undef CAST_MFMA_K
 #undef CAST_MFMA
     return hipGetLastError();
 }
@@ -840,9 +862,11 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             lds += ((size_t)1 << tb) * amp_bytes(dt);
         }
         if (dt == CAST_C128)
-            e = launch_mfma<double>(D, kind == 5, (double *)psi, (const double *)dmat, a, (int)grid, lds, stream);
+            e = launch_mfma<double>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], (double *)psi, (const double *)dmat, a,
+                                    (int)grid, lds, stream);
         else
-            e = launch_mfma<float>(D, kind == 5, (float *)psi, (const float *)dmat, a, (int)grid, lds, stream);
+            e = launch_mfma<float>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], (float *)psi, (const float *)dmat, a,
+                                   (int)grid, lds, stream);
     } else if (kind == 3) {
         DiagArgs g;
         memset(&g, 0, sizeof g);
