@@ -121,3 +121,23 @@ def test_blocked_replay_and_timed():
     ms = sv.apply_circuit_blocked_timed(fc)
     assert len(ms) == len(fc.blocked_passes(dtype)) and np.all(ms > 0)
     assert maxerr(sv.numpy(), want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("threads", [256, 1024])
+def test_blocked_workgroup_sizes(dtype, threads):
+    """The segment kernel's 256- and 1024-thread instances (both block-size
+    instances: the circuit has 3-qubit Haar gates) against the oracle."""
+    n = 15
+    gates = mixed_circuit(n, seed=13)
+    psi0 = random_state(n, seed=14, workload=9)
+    want = oracle.run_circuit(n, gates, psi0)
+    fc = cast.FusedCircuit(n, gates, k_max=3)
+    assert any(fc.gate(i)["d"] == 3 for i in range(len(fc)))
+    old = cast.get_tuning("blocked_threads", dtype)
+    cast.set_tuning("blocked_threads", threads, dtype)
+    try:
+        got = run_blocked(n, fc, psi0, dtype)
+    finally:
+        cast.set_tuning("blocked_threads", old, dtype)
+    assert maxerr(got, want) <= TOL[dtype]

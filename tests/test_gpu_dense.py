@@ -33,6 +33,38 @@ def test_dense_haar_22_vs_oracle(dtype, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
+@pytest.mark.parametrize("m3_min_d", [4, 7], ids=["3m_from_d4", "4m_only"])
+def test_dense_mfma_product_forms(dtype, tol, m3_min_d):
+    """The matrix-core passes with the three-multiplication complex product
+    at every block size (d >= 4) and with the four-product form only, on
+    direct and LDS-tile placements (a low target sends complex64 to the tile
+    kernel), against the oracle."""
+    n = 16
+    gates = dense_haar_layers(n, depth=2, seed=3)
+    gates.append(Gate("unitary", (0, 2, 5, 9), matrix=_haar(16, 5)))
+    psi0 = random_state(n, seed=2, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    old = cast.get_tuning("mfma_3m_min_d", dtype)
+    cast.set_tuning("mfma_3m_min_d", m3_min_d, dtype)
+    try:
+        sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+        fc = cast.FusedCircuit(n, gates, k_max=6)
+        kinds = {fc.pass_info(i, dtype)["kernel"] for i in range(len(fc))}
+        assert kinds & {4, 5}
+        sv.apply_circuit(fc)
+        err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    finally:
+        cast.set_tuning("mfma_3m_min_d", old, dtype)
+    print(f"dense16 {dtype} 3M from d={m3_min_d}: kernels {sorted(kinds)} err {err:.2e}", flush=True)
+    assert err <= tol
+
+
+def _haar(dim, seed):
+    from circuits import haar_unitary
+    return haar_unitary(dim, np.random.default_rng(seed))
+
+
 def _column0(g):
     return np.asarray(g.matrix, dtype=np.complex128)[:, 0]
 
