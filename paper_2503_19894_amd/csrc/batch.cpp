@@ -68,6 +68,7 @@ struct cast_batch {
     size_t mat_entries = 0, result_doubles = 0;
     std::vector<uint64_t> step_rec, step_item;
     std::vector<uint64_t> step_items;   // items per step
+    std::vector<size_t> step_lds;       // LDS bytes of each step's launch
     int nsteps = 0;
     uint64_t total_items = 0;
     cast::BatchDev dev;
@@ -154,7 +155,7 @@ static cast_status queue_program(cast_batch *b) {
             return rc;
     } else {
         for (int st = 0; st < b->nsteps; ++st)
-            if (cast_status rc = batch_launch_step(b->dev, b->dt, st, b->step_items[st], b->lds_bytes, s)) return rc;
+            if (cast_status rc = batch_launch_step(b->dev, b->dt, st, b->step_items[st], b->step_lds[st], s)) return rc;
     }
     if (cast_status rc = batch_finish(b->dev, s)) return rc;
     CAST_HIP_TRY(hipMemcpyAsync(b->h_results, b->d_results, b->result_doubles * sizeof(double),
@@ -501,6 +502,17 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         }
         if (items > 0x7fffffffull) return bail(fail(CAST_EUNSUPPORTED, "too many work items in one step"));
         b->step_items.push_back(items);
+        {
+            // LDS of this step's launch: the tables, then one tile (forward) or
+            // two (adjoint: psi and lambda) of its largest tile
+            int tbs = 0, tiles = 0;
+            for (size_t q = b->step_rec.back(); q < recs.size(); ++q) {
+                if (recs[q].kind == BK_HPSI) continue;
+                tbs = std::max(tbs, recs[q].tb);
+                tiles = std::max(tiles, recs[q].kind == BK_ADJ ? 2 : 1);
+            }
+            b->step_lds.push_back(kSegLdsExtra + (size_t)tiles * ((size_t)1 << tbs) * amp_bytes(dt));
+        }
         item_base += items;
     }
     }

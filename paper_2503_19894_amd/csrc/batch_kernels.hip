@@ -143,10 +143,19 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
-// FWD / ADJ segment on tile w of an instance.  LDS layout: psi tile, lambda
-// tile (2^tb amplitudes each), two 64-entry tables that deposit the 12 bits
-// of a run index onto the tile's high qubits, and per-gate, per-wave partial
-// sums of the segment's inner products (at most kSegMaxGates gates).
+// LDS position of tile amplitude e: 16-byte chunk c is stored at chunk
+// c ^ hash(c / 16), which keeps the coalesced load/store phases conflict-free
+// and spreads the sweeps' power-of-two-strided group reads over the banks.
+__device__ __forceinline__ uint32_t bswz(uint32_t c) { return c ^ (((c >> 4) ^ (c >> 8)) & 15u); }
+template <int S>
+__device__ __forceinline__ uint32_t bat(uint32_t e) { return (bswz(e >> S) << S) | (e & ((1u << S) - 1)); }
+
+// FWD / ADJ segment on tile w of an instance.  LDS layout: two 64-entry
+// tables that deposit the 12 bits of a run index onto the tile's high qubits,
+// per-gate, per-wave partial sums of the segment's inner products (at most
+// kSegMaxGates gates), then the psi tile and (ADJ only) the lambda tile, 2^tb
+// amplitudes each, swizzled as above.  A forward step's launch carries one
+// tile's LDS, so more of its workgroups share a compute unit.
 template <typename R>
 __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst &in, uint32_t w, double *red,
                          typename BAmp<R>::T *lds) {
@@ -154,9 +163,9 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
     constexpr int S = sizeof(V) == 16 ? 0 : 1;      // log2(amplitudes per 16-byte chunk)
     const bool adj = rec.kind == BK_ADJ;
     const uint32_t T = 1u << rec.tb;
-    V *tp = lds, *tl = lds + T;
-    uint64_t *hid = reinterpret_cast<uint64_t *>(lds + 2 * T);   // [2][64]
+    uint64_t *hid = reinterpret_cast<uint64_t *>(lds);            // [2][64]
     double *gsum = reinterpret_cast<double *>(hid + 128);         // [kSegMaxGates][4 waves][2]
+    V *tp = reinterpret_cast<V *>(reinterpret_cast<char *>(lds) + kSegLdsExtra), *tl = tp + T;
     V *psi = reinterpret_cast<V *>(in.psi);
     V *lam = reinterpret_cast<V *>(in.lam);
     uint64_t tbase = (uint64_t)w << rec.W;
@@ -181,18 +190,35 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
         return tbase | (e & wmask) | hid[r & 63] | hid[64 + (r >> 6)];
     };
     if (chunked) {
-        uint4 *t16p = reinterpret_cast<uint4 *>(tp), *t16l = reinterpret_cast<uint4 *>(tl);
-        const uint4 *p16 = reinterpret_cast<const uint4 *>(psi), *l16 = reinterpret_cast<const uint4 *>(lam);
-        for (uint32_t c = threadIdx.x; c < nchunk; c += blockDim.x) {
-            const uint64_t x = addr(c << S) >> S;
-            t16p[c] = p16[x];
-            if (adj) t16l[c] = l16[x];
+        // four chunks of each state in flight per lane
+        typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
+        nu4 *t16p = reinterpret_cast<nu4 *>(tp), *t16l = reinterpret_cast<nu4 *>(tl);
+        const nu4 *p16 = reinterpret_cast<const nu4 *>(psi), *l16 = reinterpret_cast<const nu4 *>(lam);
+        for (uint32_t c0 = threadIdx.x; c0 < nchunk; c0 += 4 * blockDim.x) {
+            nu4 bp[4], bl[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t c = c0 + u * blockDim.x;
+                if (c < nchunk) {
+                    const uint64_t x = addr(c << S) >> S;
+                    bp[u] = p16[x];
+                    if (adj) bl[u] = l16[x];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t c = c0 + u * blockDim.x;
+                if (c < nchunk) {
+                    t16p[bswz(c)] = bp[u];
+                    if (adj) t16l[bswz(c)] = bl[u];
+                }
+            }
         }
     } else {
         for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
             const uint64_t x = addr(e);
-            tp[e] = psi[x];
-            if (adj) tl[e] = lam[x];
+            tp[bat<S>(e)] = psi[x];
+            if (adj) tl[bat<S>(e)] = lam[x];
         }
     }
     __syncthreads();
@@ -218,10 +244,10 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
             if (act) {
                 base = (uint32_t)ins0(ins0(ins0(g, SW.b[0]), SW.b[1]), SW.b[2]);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) x[j] = tp[base | off[j]];
+                for (int j = 0; j < 8; ++j) x[j] = tp[bat<S>(base | off[j])];
                 if (adj) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) l[j] = tl[base | off[j]];
+                    for (int j = 0; j < 8; ++j) l[j] = tl[bat<S>(base | off[j])];
                 }
             }
             int p = SW.p0;
@@ -246,10 +272,10 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
             }
             if (act) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) tp[base | off[j]] = x[j];
+                for (int j = 0; j < 8; ++j) tp[bat<S>(base | off[j])] = x[j];
                 if (adj) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) tl[base | off[j]] = l[j];
+                    for (int j = 0; j < 8; ++j) tl[bat<S>(base | off[j])] = l[j];
                 }
             }
         }
@@ -280,14 +306,14 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
         uint4 *p16 = reinterpret_cast<uint4 *>(psi), *l16 = reinterpret_cast<uint4 *>(lam);
         for (uint32_t c = threadIdx.x; c < nchunk; c += blockDim.x) {
             const uint64_t x = addr(c << S) >> S;
-            p16[x] = t16p[c];
-            if (adj) l16[x] = t16l[c];
+            p16[x] = t16p[bswz(c)];
+            if (adj) l16[x] = t16l[bswz(c)];
         }
     } else {
         for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
             const uint64_t x = addr(e);
-            psi[x] = tp[e];
-            if (adj) lam[x] = tl[e];
+            psi[x] = tp[bat<S>(e)];
+            if (adj) lam[x] = tl[bat<S>(e)];
         }
     }
     __syncthreads();   // the LDS tables and tiles are reused by the next item
@@ -370,7 +396,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_batch_step(BatchDev d, int s) {
     __shared__ double red[4];
     const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], blockIdx.x);
-    const BatchRec rec = d.recs[r];
+    const BatchRec &rec = d.recs[r];   // by reference: its qhi[] is indexed at run time
     run_item<R>(d, rec, blockIdx.x - rec.item0, red);
 }
 
@@ -408,7 +434,7 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
             const int s = (int)lo;
             const uint64_t x = item - d.step_item[s];
             const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], x);
-            const BatchRec rec = d.recs[r];
+            const BatchRec &rec = d.recs[r];   // by reference: its qhi[] is indexed at run time
             if (threadIdx.x == 0) {
                 unsigned long long *done = &counters[2 + rec.inst];
                 if (pend && pend_inst != rec.inst) {
