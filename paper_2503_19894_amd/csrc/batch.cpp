@@ -28,6 +28,7 @@ struct InstPlan {
     std::vector<cast_gate> gates;          // copied descriptors
     std::vector<std::vector<cplx>> fixed;  // fixed matrices (sorted-qubit order), per gate
     std::vector<int> sq0, sq1;             // sorted targets per gate
+    std::vector<int> form;                 // BatchForm of each gate's matrix (all parameter values)
     std::vector<uint32_t> xl, zl;          // local generator masks per gate
     std::vector<int> gen_sorted;           // generator letters in sorted local order
     std::vector<uint64_t> gx, gz;          // global generator masks per gate
@@ -248,6 +249,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         ip.gates.assign(circuits[i], circuits[i] + n_gates[i]);
         const size_t L = ip.gates.size();
         ip.fixed.resize(L);
+        ip.form.assign(L, BF_GENERAL);
         ip.sq0.resize(L);
         ip.sq1.resize(L);
         ip.xl.assign(L, 0);
@@ -288,6 +290,28 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 if (letter == 1 || letter == 2) ip.gx[l] |= 1ull << q, ip.xl[l] |= 1u << lb;
                 if (letter == 2 || letter == 3) ip.gz[l] |= 1ull << q, ip.zl[l] |= 1u << lb;
                 ip.gen_sorted[l] |= letter << (2 * lb);
+            }
+            // form: exp(-i a P / 2) = cos I - i sin P is diagonal when P has no X or Y
+            // letter and real when P has an odd number of Y letters (P imaginary);
+            // a fixed gate's form is read off its matrix
+            if (g.param_id >= 0) {
+                int nx = 0, ny = 0;
+                for (int a = 0; a < g.k; ++a) {
+                    const int letter = (g.generator >> (2 * a)) & 3;
+                    nx += letter == 1;
+                    ny += letter == 2;
+                }
+                if (nx == 0 && ny == 0) ip.form[l] = BF_DIAG;
+                else if (ny % 2 == 1) ip.form[l] = BF_REAL;
+            } else {
+                bool diag = true, real = true;
+                for (int r = 0; r < D; ++r)
+                    for (int c = 0; c < D; ++c) {
+                        const cplx z = ip.fixed[l][(size_t)r * D + c];
+                        if (r != c && z != cplx(0, 0)) diag = false;
+                        if (z.imag() != 0.0) real = false;
+                    }
+                ip.form[l] = diag ? BF_DIAG : real ? BF_REAL : BF_GENERAL;
             }
             ip.mat_fwd[l] = mat_entries;
             mat_entries += (uint64_t)D * D;
@@ -486,6 +510,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                             if ((ip.zl[l] >> bb) & 1u) sgt.zl |= 1u << sb;
                         }
                         sgt.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
+                        sgt.form = ip.form[l];
                         if (sgt.slot >= 0) ++nparam;
                         segs.push_back(sgt);
                     }

@@ -35,7 +35,13 @@ struct SegGate {            // one gate of a sweep, in sweep coordinates
     int slot;               // ADJ: result slot, or -1
     uint32_t xl, zl;        // ADJ: generator x/z masks over the sweep bits
     uint64_t mat;           // offset (complex entries) of U (FWD) or U^dag (ADJ)
+    int form;               // matrix form for every parameter value: BF_GENERAL, BF_DIAG or BF_REAL
+    int pad;
 };
+
+// Matrix forms the register sweeps specialise (fewer multiplies): diagonal
+// (e.g. RZ, RZZ, CZ) and real (e.g. RY).
+enum BatchForm : int { BF_GENERAL = 0, BF_DIAG = 1, BF_REAL = 2 };
 
 struct SegSweep {           // consecutive gates of a segment on at most three tile bits
     int b[3];               // the sweep's tile bits, ascending

@@ -94,8 +94,91 @@ __device__ __forceinline__ void reg_apply2(V *x, const R *m) {
     }
 }
 
+// Diagonal gate on sweep bits (B0, B1; B1 < 0 for one qubit): x[j] *= D[j's bits].
+template <int B0, int B1, typename V, typename R>
+__device__ __forceinline__ void reg_diag(V *x, const R *m) {
+    constexpr int K = B1 < 0 ? 1 : 2, DIM = 1 << K;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int loc = ((j >> B0) & 1) | (B1 < 0 ? 0 : ((j >> (B1 < 0 ? 0 : B1)) & 1) << 1);
+        const R dr = m[2 * (loc * DIM + loc)], di = m[2 * (loc * DIM + loc) + 1];
+        const V a = x[j];
+        x[j].x = dr * a.x - di * a.y;
+        x[j].y = dr * a.y + di * a.x;
+    }
+}
+
+// Real matrix: only the real parts of the entries are read (two multiplies per entry).
+template <int B, typename V, typename R>
+__device__ __forceinline__ void reg_real1(V *x, const R *m) {
+    const R m00 = m[0], m01 = m[2], m10 = m[4], m11 = m[6];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (j & (1 << B)) continue;
+        const int j1 = j | (1 << B);
+        const V a = x[j], b = x[j1];
+        x[j].x = fma(m00, a.x, m01 * b.x);
+        x[j].y = fma(m00, a.y, m01 * b.y);
+        x[j1].x = fma(m10, a.x, m11 * b.x);
+        x[j1].y = fma(m10, a.y, m11 * b.y);
+    }
+}
+
+template <int B0, int B1, typename V, typename R>
+__device__ __forceinline__ void reg_real2(V *x, const R *m) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (j & ((1 << B0) | (1 << B1))) continue;
+        const int idx[4] = {j, j | (1 << B0), j | (1 << B1), j | (1 << B0) | (1 << B1)};
+        V in[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) in[c] = x[idx[c]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            R ar = 0, ai = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                ar = fma(m[2 * (r * 4 + c)], in[c].x, ar);
+                ai = fma(m[2 * (r * 4 + c)], in[c].y, ai);
+            }
+            x[idx[r]].x = ar;
+            x[idx[r]].y = ai;
+        }
+    }
+}
+
 template <typename V, typename R>
 __device__ __forceinline__ void reg_apply(const SegGate &G, V *x, const R *m) {
+    if (G.form == BF_DIAG) {
+        if (G.k == 1) {
+            switch (G.t0) {
+                case 0: reg_diag<0, -1>(x, m); break;
+                case 1: reg_diag<1, -1>(x, m); break;
+                default: reg_diag<2, -1>(x, m); break;
+            }
+        } else if (G.t0 == 0) {
+            if (G.t1 == 1) reg_diag<0, 1>(x, m);
+            else reg_diag<0, 2>(x, m);
+        } else {
+            reg_diag<1, 2>(x, m);
+        }
+        return;
+    }
+    if (G.form == BF_REAL) {
+        if (G.k == 1) {
+            switch (G.t0) {
+                case 0: reg_real1<0>(x, m); break;
+                case 1: reg_real1<1>(x, m); break;
+                default: reg_real1<2>(x, m); break;
+            }
+        } else if (G.t0 == 0) {
+            if (G.t1 == 1) reg_real2<0, 1>(x, m);
+            else reg_real2<0, 2>(x, m);
+        } else {
+            reg_real2<1, 2>(x, m);
+        }
+        return;
+    }
     if (G.k == 1) {
         switch (G.t0) {
             case 0: reg_apply1<0>(x, m); break;
