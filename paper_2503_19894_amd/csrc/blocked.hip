@@ -147,36 +147,50 @@ __device__ __forceinline__ void commit(char *area, const Prefetch &pf, const Blk
     }
 }
 
-// A run of m diagonal gates: amplitude y is read once, multiplied by each
+// A run of M diagonal gates: amplitude y is read once, multiplied by each
 // gate's phase D_t[j_t(y)] in order (identity phases are exactly 1), and
-// written once.
-template <typename R, int S, int NT>
-__device__ __forceinline__ void diag_run(typename Cx<R>::T *tile, const char *area, const BlkGate *gates,
-                                         uint32_t gi, uint32_t tile_amps) {
+// written once.  Instantiated per run length so the phase loop is straight
+// code.
+template <typename R, int S, int NT, int M>
+__device__ __forceinline__ void diag_run_m(typename Cx<R>::T *tile, const char *area, const BlkGate *gates,
+                                           uint32_t gi, uint32_t tile_amps) {
     using V = typename Cx<R>::T;
-    const int m = gates[gi].run;
     const int ts = gates[gi].tshift;
     const V *tabs = reinterpret_cast<const V *>(area + kBlkAreaHead);
     const uint2 *itab = reinterpret_cast<const uint2 *>(area + kBlkIterOff);
     const uint32_t *jt = reinterpret_cast<const uint32_t *>(area + kBlkJOff);
-    uint32_t jl[kBlkRunMax];
+    uint32_t jl[M];
 #pragma unroll
-    for (int t = 0; t < (int)kBlkRunMax; ++t) jl[t] = t < m ? loc(threadIdx.x, gates[gi + t]) : 0u;
+    for (int t = 0; t < M; ++t) jl[t] = loc(threadIdx.x, gates[gi + t]) | ((uint32_t)t << ts);
     const uint32_t al = at<S>(threadIdx.x);
     const uint32_t iters = tile_amps / NT;
     for (uint32_t i = 0; i < iters; ++i) {
         const uint32_t a = al ^ itab[i].y;
         V x = tile[a];
 #pragma unroll
-        for (int t = 0; t < (int)kBlkRunMax; ++t) {
-            if (t >= m) break;
-            const V ph = tabs[(t << ts) + (jl[t] ^ jt[t * kBlkMaxIters + i])];
+        for (int t = 0; t < M; ++t) {
+            const V ph = tabs[jl[t] ^ jt[t * kBlkMaxIters + i]];
             const R re = x.x * ph.x - x.y * ph.y;
             const R im = x.x * ph.y + x.y * ph.x;
             x.x = re;
             x.y = im;
         }
         tile[a] = x;
+    }
+}
+
+template <typename R, int S, int NT>
+__device__ __forceinline__ void diag_run(typename Cx<R>::T *tile, const char *area, const BlkGate *gates,
+                                         uint32_t gi, uint32_t tile_amps) {
+    switch (gates[gi].run) {
+        case 1: diag_run_m<R, S, NT, 1>(tile, area, gates, gi, tile_amps); break;
+        case 2: diag_run_m<R, S, NT, 2>(tile, area, gates, gi, tile_amps); break;
+        case 3: diag_run_m<R, S, NT, 3>(tile, area, gates, gi, tile_amps); break;
+        case 4: diag_run_m<R, S, NT, 4>(tile, area, gates, gi, tile_amps); break;
+        case 5: diag_run_m<R, S, NT, 5>(tile, area, gates, gi, tile_amps); break;
+        case 6: diag_run_m<R, S, NT, 6>(tile, area, gates, gi, tile_amps); break;
+        case 7: diag_run_m<R, S, NT, 7>(tile, area, gates, gi, tile_amps); break;
+        default: diag_run_m<R, S, NT, 8>(tile, area, gates, gi, tile_amps); break;
     }
 }
 
