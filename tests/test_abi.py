@@ -12,6 +12,7 @@ import paper_2503_19894_amd as cast
 from circuits import Gate
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EINVAL = -1   # cast_status CAST_EINVAL
 
 
 def declared_functions():
@@ -117,3 +118,25 @@ def test_batch_create_validation():
         cast.Batch([gates], [4], [P - 1], [H])                      # param_id out of range
     with pytest.raises(cast.CastError):
         cast.Batch([gates], [4], [P], [H], mode=5)
+
+
+def test_blocked_entry_points_validation():
+    """The cache-blocked queries fail cleanly (no device work) on a wrong
+    qubit count, a bad dtype, an index out of range or NULL arguments, and
+    answer for a valid list without a GPU."""
+    import ctypes
+
+    from circuits import qft
+    fc = cast.FusedCircuit(14, qft(14), k_max=4)
+    npass = ctypes.c_size_t()
+    assert cast._lib.blocked_info(fc.handle, 13, cast.C128, ctypes.byref(npass)) == EINVAL
+    assert cast._lib.blocked_info(fc.handle, 14, 7, ctypes.byref(npass)) == EINVAL
+    assert cast._lib.blocked_info(None, 14, cast.C128, ctypes.byref(npass)) == EINVAL
+    assert cast._lib.blocked_info(fc.handle, 14, cast.C128, None) == EINVAL
+    assert cast._lib.blocked_info(fc.handle, 14, cast.C128, ctypes.byref(npass)) == 0
+    assert 1 <= npass.value < len(fc)
+    first = ctypes.c_size_t()
+    assert cast._lib.blocked_pass_info(fc.handle, 14, cast.C128, npass.value, ctypes.byref(first), None, None,
+                                       None, None) == EINVAL
+    assert cast._lib.blocked_pass_info(fc.handle, 14, cast.C128, 0, None, None, None, None, None) == 0
+    assert cast._lib.apply_circuit_blocked(None, fc.handle) == EINVAL
