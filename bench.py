@@ -193,6 +193,54 @@ def run_families(n=30, dtype_names=("c128", "c64")):
     return out
 
 
+def run_jit():
+    """Generated (immediate-valued) kernels against the library kernels: the
+    paper's single-gate table workload (H and U3 on 2 and 3 qubits, one fused
+    pass, 28 qubits, high and low targets; GiBps counts the state once as the
+    paper does) and QFT-30, both dtypes."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import gate_sweep, qft, random_state_torch
+
+    out = {}
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        amp = 16 if dname == "c128" else 8
+        res = {}
+        n = 30
+        psi = random_state_torch(n, seed=0, device="cuda", dtype=dt)
+        sv = cast.StateVector(n, tensor=psi)
+        fc = cast.FusedCircuit(n, qft(n), k_max=5)
+        nk, cms = fc.jit_compile(dt)
+        sv.apply_circuit(fc)
+        sv.apply_circuit_jit(fc)
+        res["qft30"] = {"library_ms": min(float(sv.apply_circuit_timed(fc).sum()) for _ in range(2)),
+                        "generated_ms": min(float(sv.apply_circuit_jit_timed(fc).sum()) for _ in range(2)),
+                        "kernels": nk, "compile_ms": round(cms, 1)}
+        del sv, psi
+        torch.cuda.empty_cache()
+        n = 28
+        psi = random_state_torch(n, seed=1, device="cuda", dtype=dt)
+        sv = cast.StateVector(n, tensor=psi)
+        S = (1 << n) * amp
+        for kind in ("h", "u3"):
+            for k in (2, 3):
+                for place, qs in (("high", tuple(range(n - k, n))), ("low", tuple(range(k)))):
+                    fc = cast.FusedCircuit(n, gate_sweep(kind, k, qs, seed=k), k_max=k)
+                    fc.jit_compile(dt)
+                    sv.apply_circuit(fc)
+                    sv.apply_circuit_jit(fc)
+                    t1 = float(np.median([sv.apply_circuit_timed(fc).sum() for _ in range(5)]))
+                    t2 = float(np.median([sv.apply_circuit_jit_timed(fc).sum() for _ in range(5)]))
+                    res[f"{kind}x{k}_{place}"] = {"library_gibps": S / (t1 * 1e-3) / 2**30,
+                                                  "generated_gibps": S / (t2 * 1e-3) / 2**30}
+        del sv, psi
+        torch.cuda.empty_cache()
+        out[dname] = res
+    return out
+
+
 def run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, per_pass_ms):
     """The same fused circuit cache-blocked (several fused gates per HBM
     pass): HBM passes, time per step, the passes' HBM rate (every pass reads
@@ -528,6 +576,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device copy of exactly 1 GiB (reference for HBM byte counters)")
     ap.add_argument("--summarize-kernel-trace", nargs="+", metavar="STATS_CSV COMMAND [NAME_FILTER]")
+    ap.add_argument("--jit", action="store_true",
+                    help="only the generated-kernel comparison (paper's single-gate table workload, QFT-30)")
     ap.add_argument("--families", action="store_true",
                     help="only the circuit-family table (fusion none / size-only / adaptive, per pass and "
                          "cache-blocked); prints one JSON object")
@@ -559,6 +609,9 @@ def main():
         return
     if args.families:
         print(json.dumps(run_families(args.n)), flush=True)
+        return
+    if args.jit:
+        print(json.dumps(run_jit()), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

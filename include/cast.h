@@ -209,6 +209,30 @@ cast_status blocked_info(const cast_fused *f, int n, cast_dtype dt, size_t *n_pa
 cast_status blocked_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
                               int *tile_bits, int *window, int *high_qubits);
 
+/* ------------------------------------------------------------ dynamic kernels */
+
+/* Generated kernels (the paper's run-time generated, gate-specific kernels,
+ * Sec. IV-A): one kernel per fused gate with block dimension d <= 4, written
+ * from the gate's matrix cast to dt with every entry an immediate constant,
+ * exact zeros dropped entry by entry, entries +-1 and +-i turned into
+ * additions, and amplitudes that share a coefficient (up to sign) within an
+ * output row summed before one multiplication; target masks and block
+ * offsets are constants too.  All kernels of the list are compiled for
+ * gfx950 with hipRTC in one program, on the host, and cached in the fused
+ * list.  jit_compile compiles (no device needed) and reports the kernel
+ * count and compile time (ms). */
+cast_status jit_compile(const cast_fused *f, cast_dtype dt, int *n_kernels, double *compile_ms);
+
+/* Applies the fused list with the generated kernels (compiling them first if
+ * needed and loading them on the device at first use); gates with d > 4 run
+ * with the library's kernels.  Same result as apply_circuit up to rounding.
+ * Queued on the state's stream. */
+cast_status apply_circuit_jit(cast_sv *sv, const cast_fused *f);
+
+/* Same, with a HIP event pair around every pass (n_fused floats, ms).
+ * Synchronous.  For measurement. */
+cast_status apply_circuit_jit_timed(cast_sv *sv, const cast_fused *f, float *pass_ms);
+
 /* Frees a fused list.  NULL-safe.  The caller must not destroy a list while
  * work that uses it is still queued (synchronise the stream first). */
 void fused_destroy(cast_fused *f);

@@ -78,6 +78,9 @@ SIGNATURES = {
     "blocked_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                          _c_int_p, _c_int_p, _c_int_p]),
+    "jit_compile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p, _c_double_p]),
+    "apply_circuit_jit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "apply_circuit_jit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
                                     ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
@@ -317,6 +320,14 @@ class FusedCircuit:
                         "high_qubits": tuple(q for q in hq if q >= 0)})
         return out
 
+    def jit_compile(self, dtype):
+        """Compiles the generated kernels for `dtype` (host only); returns
+        (kernel count, compile ms)."""
+        dt = C128 if dtype == torch.complex128 else C64
+        nk, ms = ctypes.c_int(), ctypes.c_double()
+        jit_compile(self.handle, dt, ctypes.byref(nk), ctypes.byref(ms))
+        return nk.value, ms.value
+
     def __len__(self):
         return self.info()["n_fused"]
 
@@ -370,6 +381,17 @@ class StateVector:
         out = (ctypes.c_float * max(1, npass))()
         apply_circuit_blocked_timed(self.handle, fused.handle, out)
         return np.array(out[:npass], dtype=np.float64)
+
+    def apply_circuit_jit(self, fused: FusedCircuit):
+        """Applies the circuit with its generated (immediate-valued) kernels."""
+        apply_circuit_jit(self.handle, fused.handle)
+
+    def apply_circuit_jit_timed(self, fused: FusedCircuit):
+        """Applies the circuit with its generated kernels; per-pass device times (ms)."""
+        nf = len(fused)
+        out = (ctypes.c_float * max(1, nf))()
+        apply_circuit_jit_timed(self.handle, fused.handle, out)
+        return np.array(out[:nf], dtype=np.float64)
 
     def expval(self, terms):
         arr = pauli_terms(terms)

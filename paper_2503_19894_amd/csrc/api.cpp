@@ -599,7 +599,7 @@ cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt,
 
 void fused_destroy(cast_fused *f) {
     if (!f) return;
-    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr), blocked_free(f->blocked[d]);
+    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr), blocked_free(f->blocked[d]), jit_free(f->jit[d]);
     delete f;
 }
 

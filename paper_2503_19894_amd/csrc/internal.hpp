@@ -153,6 +153,8 @@ struct cast_sv {
 namespace cast {
 struct BlockedPlan;                  // cache-blocked grouping of a fused list (blocked.cpp)
 void blocked_free(BlockedPlan *b);
+struct JitModule;                    // generated kernels of a fused list (jit.cpp)
+void jit_free(JitModule *j);
 }  // namespace cast
 
 struct cast_fused {
@@ -164,4 +166,6 @@ struct cast_fused {
     std::vector<size_t> dev_off[3];
     // cache-blocked grouping, per dtype (built on first use)
     cast::BlockedPlan *blocked[3] = {nullptr, nullptr, nullptr};
+    // generated kernels, per dtype (compiled on first use)
+    cast::JitModule *jit[3] = {nullptr, nullptr, nullptr};
 };
