@@ -60,14 +60,6 @@ __device__ __forceinline__ uint32_t loc(uint32_t y, const BlkGate &g) {
     return j;
 }
 
-// Loop iterations of the workgroup over a gate's work items (amplitudes for
-// a diagonal gate, cosets of the span for a block gate).
-template <int NT>
-__device__ __forceinline__ uint32_t iters_of(const BlkGate &g, uint32_t tile_amps) {
-    const uint32_t items = tile_amps >> (g.kind == 0 ? 0 : g.d);
-    return (items + NT - 1) / NT;
-}
-
 // Staging of a gate area in two halves: the matrices (or a diagonal run's
 // phase tables) are read from global memory into registers before the
 // current gate is applied, so their latency hides behind it, and written to

@@ -14,7 +14,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
-#include <map>
 #include <string>
 
 #include "internal.hpp"
