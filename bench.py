@@ -154,14 +154,16 @@ def run_families(n=30, dtype_names=("c128", "c64")):
     """Synthetic stand-ins of the paper's circuit families (QFT, IQP, ALA,
     QVC, RQC, HES) on n qubits from a random state: for each fusion setting
     (none = k_max 1, size-only k_max 5, adaptive k_max 5 with the measured
-    cost table) the fused-gate count, host fusion time, one-pass-per-gate time
-    and cache-blocked time (one warm-up application each, then one timed)."""
+    cost table, and size-only k_max 2, 3, 4) the fused-gate count, host fusion
+    time, one-pass-per-gate time and cache-blocked time (one warm-up
+    application each, then one timed)."""
     import torch
 
     import paper_2503_19894_amd as cast
     from circuits import FAMILIES, random_state_torch
 
-    modes = {"none": dict(k_max=1), "size": dict(k_max=5), "adaptive": dict(k_max=5, cost_model=1)}
+    modes = {"none": dict(k_max=1), "size": dict(k_max=5), "adaptive": dict(k_max=5, cost_model=1),
+             "size_k2": dict(k_max=2), "size_k3": dict(k_max=3), "size_k4": dict(k_max=4)}
     out = {}
     for dname in dtype_names:
         dtype = torch.complex128 if dname == "c128" else torch.complex64
