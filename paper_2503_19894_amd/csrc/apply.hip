@@ -93,6 +93,20 @@ __device__ __forceinline__ void st(V *p, const V &v) {
     }
 }
 
+// Item i of a block-decomposed pass: items are cut into 64-item slices (one
+// wave each, 64 consecutive groups) and the block slot varies fastest across
+// slices, so the blocks of the same groups are processed close together in
+// time.  Their amplitudes often share cache lines (always when a target is
+// below the line size), and a block-slowest order would stream the state from
+// HBM once per block.  Needs ngroups to be a multiple of 64; the slice count
+// stays below 2^28 for n <= 34.
+__device__ __forceinline__ void direct_item(uint64_t i, uint32_t nblk, uint32_t &bs, uint64_t &g) {
+    const uint32_t s = __builtin_amdgcn_readfirstlane((uint32_t)(i >> 6));
+    const uint32_t gs = s / nblk;
+    bs = s - gs * nblk;
+    g = ((uint64_t)gs << 6) | (i & 63);
+}
+
 template <int D, typename R, int IPT, bool NT>
 __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *__restrict__ mat,
                                                 PassArgs a) {
@@ -109,9 +123,9 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
 #pragma unroll
         for (int u = 0; u < IPT; ++u) {
             const uint64_t i = it * per_iter + (uint64_t)u * 256 + threadIdx.x;
-            // every 64-lane slice lies inside one block's run of ngroups items
-            const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(i >> a.log_ngroups));
-            const uint64_t g = i & (a.ngroups - 1);
+            uint32_t bs;
+            uint64_t g;
+            direct_item(i, a.nblk, bs, g);
             const uint32_t bid = a.blk[bs];
             uint64_t b = deposit(g, a.lowmask, a.k);
             for (int j = 0; j < a.k - D; ++j)
@@ -138,8 +152,9 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
     // tail: items not covered by full iterations, one per thread
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t i = nfull * per_iter + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += stride) {
-        const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(i >> a.log_ngroups));
-        const uint64_t g = i & (a.ngroups - 1);
+        uint32_t bs;
+        uint64_t g;
+        direct_item(i, a.nblk, bs, g);
         const uint32_t bid = a.blk[bs];
         uint64_t b = deposit(g, a.lowmask, a.k);
         for (int j = 0; j < a.k - D; ++j)
@@ -560,9 +575,13 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15;
     const uint64_t upb = a.ngroups >> 4;   // units per block
     const uint64_t units = upb * a.nblk;
+    // the block slot varies fastest across units (as in the direct kernel);
+    // units number below 2^26 for n <= 34
     for (uint64_t u = (uint64_t)blockIdx.x * 4 + wave; u < units; u += (uint64_t)gridDim.x * 4) {
-        const uint32_t bs = __builtin_amdgcn_readfirstlane((uint32_t)(u / upb));
-        const uint64_t g = (u % upb) * 16 + j;
+        const uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        const uint32_t gu = uu / a.nblk;
+        const uint32_t bs = uu - gu * a.nblk;
+        const uint64_t g = (uint64_t)gu * 16 + j;
         const uint32_t bid = a.blk[bs];
         uint64_t base = deposit(g, a.lowmask, a.k);
         for (int q = 0; q < a.k - D; ++q)
@@ -919,7 +938,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
         a.log_ngroups = n - k;
         a.ngroups = 1ull << (n - k);
-        // ngroups >= 64 (n - k >= 6), so every 64-lane slice of items shares a block
+        // ngroups >= 64 (n - k >= 6): a 64-item slice is 64 consecutive groups of one block
         if (dt == CAST_C128)
             e = launch_direct<double>(D, dt, (double *)psi, (const double *)dmat, a, stream);
         else
