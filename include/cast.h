@@ -253,7 +253,10 @@ void fused_destroy(cast_fused *f);
  * at most 64 KiB, so two workgroups share a compute unit's LDS),
  * "blocked_threads" (their workgroup size: 256, 512 or 1024),
  * "mfma_3m_min_d" (matrix-core passes with blocks of d >= this value form
- * complex products with three real products instead of four; 4..7, 7 = never).
+ * complex products with three real products instead of four; 4..7, 7 = never),
+ * "mfma_low_tile" (1: a matrix-core pass with d <= 4 and a target below bit 4
+ * runs on the LDS tile when at most one target lies above the tile's
+ * contiguous window or the gate has several blocks; 0: the direct gather).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);

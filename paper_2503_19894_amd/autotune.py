@@ -40,6 +40,7 @@ KNOB_CHOICES = [
     ("diag_lds_table", [0, 1]),
     ("diag_order", [0, 1]),
     ("mfma_3m_min_d", [4, 5, 6, 7]),
+    ("mfma_low_tile", [0, 1]),
 ]
 
 
@@ -60,6 +61,9 @@ def suite(n, dtype):
                   (3, (2, 9, 20)), (2, (0, 15))):
         items.append(cast.FusedCircuit(n, [Gate("unitary", qs, matrix=haar_unitary(1 << k, rng))], k_max=k))
     items.append(cast.FusedCircuit(n, gate_sweep("x", 3, (0, 1, 2)), k_max=3))
+    # low targets, two 16-dimensional blocks (the Ising-chain shape)
+    items.append(cast.FusedCircuit(n, [Gate("unitary", (0, 1, 2, 3, 4), matrix=structured_unitary(5, 4, rng))],
+                                   k_max=5))
     return items
 
 

@@ -45,6 +45,7 @@ Tuning &tuning() {
         env("CAST_MFMA_MIN_D", x.mfma_min_d);
         env("CAST_MFMA_GRID_PER_CU", x.mfma_grid_per_cu);
         env("CAST_MFMA_DIRECT_MIN_Q", x.mfma_direct_min_q);
+        env("CAST_MFMA_LOW_TILE", x.mfma_low_tile);
         env("CAST_MFMA_3M_MIN_D", x.mfma_3m_min_d);
         env("CAST_BLOCKED_TILE_BITS", x.blocked_tile_bits);
         env("CAST_BLOCKED_THREADS", x.blocked_threads);
@@ -403,6 +404,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "mfma_min_d") { *lo = 4; *hi = 7; return &t.mfma_min_d[i]; }
     if (key == "mfma_grid_per_cu") { *lo = 1; *hi = 16; return &t.mfma_grid_per_cu[i]; }
     if (key == "mfma_direct_min_q") { *hi = 34; return &t.mfma_direct_min_q[i]; }
+    if (key == "mfma_low_tile") { *hi = 1; return &t.mfma_low_tile[i]; }
     if (key == "mfma_3m_min_d") { *lo = 4; *hi = 7; return &t.mfma_3m_min_d[i]; }
     if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 13 : 12; return &t.blocked_tile_bits[i]; }
     if (key == "blocked_threads") { *lo = 256; *hi = 1024; return &t.blocked_threads[i]; }

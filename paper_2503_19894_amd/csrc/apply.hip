@@ -758,11 +758,37 @@ static hipError_t launch_diag(int U, bool lds_table, R *psi, const R *m, const D
 // re-reads inputs from LDS (TWOBUF).
 static int max_reg_d(cast_dtype dt) { return dt == CAST_C128 ? 5 : 5; }
 
+static int mfma_tile_bits(int n, cast_dtype dt, const PassPlan &p);
+
+// Targets at or above the MFMA tile's contiguous window: the smallest kH with
+// #{targets >= tb - kH} == kH.
+static int mfma_tile_khi(int n, cast_dtype dt, const PassPlan &p) {
+    const int tb = mfma_tile_bits(n, dt, p);
+    for (int khi = 0;; ++khi) {
+        int cnt = 0;
+        for (int i = 0; i < p.k; ++i) cnt += p.q[i] >= tb - khi;
+        if (cnt == khi) return khi;
+    }
+}
+
+// The direct MFMA gather puts 16 groups on the 16 lanes of a row; with a
+// target below bit 4 those groups are not consecutive amplitudes, so each load
+// collects scattered 16-byte pieces (more scattered still when the plan has
+// several blocks, whose basis offsets are XOR combinations of the targets).
+// The LDS tile reads runs of 2^(tb - kH) consecutive amplitudes instead, and
+// wins for d <= 4 when at most one target lies above the window or the plan
+// has several blocks.  At d = 5 a tile holds too few 32-amplitude groups to
+// keep the matrix cores busy, and the direct gather stays ahead.
+static bool mfma_prefer_tile(int n, cast_dtype dt, const PassPlan &p) {
+    if (!tuning().mfma_low_tile[dt] || p.q[0] >= 4 || p.d > 4) return false;
+    return p.blk.size() > 1 || mfma_tile_khi(n, dt, p) <= 1;
+}
+
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p) {
     const Tuning &tu = tuning();
     if (p.d == 0 && tu.use_diag[dt]) return 3;
     if (p.d >= tu.mfma_min_d[dt] && mfma_fits(n, dt, p)) {
-        if (p.q[0] >= tu.mfma_direct_min_q[dt] && (n - p.k) >= 4) return 4;
+        if (p.q[0] >= tu.mfma_direct_min_q[dt] && (n - p.k) >= 4 && !mfma_prefer_tile(n, dt, p)) return 4;
         return 5;
     }
     if (p.d > max_reg_d(dt)) return 2;
@@ -853,12 +879,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             if (grid > cap) grid = cap;
         } else {
             const int tb = mfma_tile_bits(n, dt, p);
-            int khi = 0;
-            for (;; ++khi) {
-                int cnt = 0;
-                for (int i = 0; i < k; ++i) cnt += p.q[i] >= tb - khi;
-                if (cnt == khi) break;
-            }
+            const int khi = mfma_tile_khi(n, dt, p);
             const int W = tb - khi;
             a.tb = tb;
             a.W = W;

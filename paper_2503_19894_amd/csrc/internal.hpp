@@ -78,6 +78,7 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int mfma_min_d[3] = {0, 4, 4};   // smallest block dimension sent to the MFMA kernels
     int mfma_grid_per_cu[3] = {0, 4, 4};
     int mfma_direct_min_q[3] = {0, 4, 4};  // smallest target for the MFMA direct gather
+    int mfma_low_tile[3] = {0, 1, 1};  // low-target d <= 4 MFMA passes on the LDS tile when its runs are long
     int mfma_3m_min_d[3] = {0, 6, 6};  // matrix cores: three-multiplication complex product from this d (7: never)
     int blocked_tile_bits[3] = {0, 13, 12};  // cache-blocked passes: log2(amplitudes per LDS tile)
     int blocked_threads[3] = {0, 512, 512};  // cache-blocked passes: threads per workgroup (256, 512, 1024)

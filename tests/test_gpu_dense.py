@@ -60,6 +60,39 @@ def test_dense_mfma_product_forms(dtype, tol, m3_min_d):
     assert err <= tol
 
 
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
+@pytest.mark.parametrize("low_tile", [0, 1], ids=["direct", "tile"])
+def test_low_target_mfma_placement(dtype, tol, low_tile):
+    """Matrix-core passes with a target below bit 4: two 5-qubit gates made
+    of two 16-dimensional blocks (Haar on four targets times a phase on the
+    fifth; contiguous low targets, and low targets plus two high ones) and a
+    single-block 4-qubit gate, on the direct gather (mfma_low_tile 0) and on
+    the LDS tile (1), against the oracle."""
+    n = 18
+    rng = np.random.default_rng(11)
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, 2))
+    two_blocks = np.kron(np.diag(ph), _haar(16, 12))
+    gates = [Gate("unitary", (0, 1, 2, 3, 4), matrix=two_blocks),
+             Gate("unitary", (0, 1, 2, 16, 17), matrix=np.kron(np.diag(ph[::-1]), _haar(16, 13))),
+             Gate("unitary", (1, 2, 3, 6), matrix=_haar(16, 14))]
+    psi0 = random_state(n, seed=4, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    old = cast.get_tuning("mfma_low_tile", dtype)
+    cast.set_tuning("mfma_low_tile", low_tile, dtype)
+    try:
+        fc = cast.FusedCircuit(n, gates, k_max=1)   # each gate its own pass
+        info = [(fc.gate(i)["d"], fc.gate(i)["active_blocks"], fc.pass_info(i, dtype)["kernel"]) for i in range(len(fc))]
+        sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+        sv.apply_circuit(fc)
+        err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    finally:
+        cast.set_tuning("mfma_low_tile", old, dtype)
+    print(f"low-target mfma {dtype} low_tile={low_tile}: (d, blocks, kernel) {info} err {err:.2e}", flush=True)
+    assert [i[:2] for i in info] == [(4, 2), (4, 2), (4, 1)]
+    assert {i[2] for i in info} == ({5} if low_tile else {4})
+    assert err <= tol
+
+
 def _haar(dim, seed):
     from circuits import haar_unitary
     return haar_unitary(dim, np.random.default_rng(seed))
