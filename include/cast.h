@@ -242,7 +242,9 @@ void fused_destroy(cast_fused *f);
 /* Launch knobs of the pass kernels, per dtype (dt = CAST_C64 or CAST_C128).  Keys: "direct_min_q" (smallest
  * target for the direct gather), "tile_bits" (log2 amplitudes per LDS tile),
  * "direct_ipt" (work items per thread: 1, 2 or 4), "direct_nt" (non-temporal
- * hints 0/1), "max_grid" (workgroup cap), "use_diag" (elementwise diagonal
+ * hints 0/1), "direct_chunk_log" (direct kernel on a gate with several blocks:
+ * log2 of the consecutive groups one block runs over before the next block
+ * takes the same groups, 6..16), "max_grid" (workgroup cap), "use_diag" (elementwise diagonal
  * kernel 0/1), "mfma_min_d" (smallest block dimension for the matrix cores,
  * 4..7; 7 disables them), "mfma_grid_per_cu", "mfma_direct_min_q",
  * "diag_unroll" (diagonal kernel chunks per thread: 1, 2, 4, 8),

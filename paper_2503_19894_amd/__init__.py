@@ -221,12 +221,12 @@ def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, aggl
 
 
 # --------------------------------------------------------------------- tuning
-TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "max_grid", "use_diag", "mfma_min_d",
+TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "direct_chunk_log", "max_grid", "use_diag", "mfma_min_d",
                "mfma_grid_per_cu", "mfma_direct_min_q", "diag_unroll", "diag_max_grid", "diag_lds_table",
                "diag_order", "blocked_tile_bits", "blocked_threads", "mfma_3m_min_d", "mfma_low_tile")
 #: environment overrides (set for sweeps) take precedence over the tuning file
 _ENV_OF = {"direct_min_q": "CAST_DIRECT_MIN_Q", "tile_bits": "CAST_TILE_BITS", "direct_ipt": "CAST_DIRECT_IPT",
-           "direct_nt": "CAST_DIRECT_NT", "max_grid": "CAST_MAX_GRID", "use_diag": "CAST_USE_DIAG",
+           "direct_nt": "CAST_DIRECT_NT", "direct_chunk_log": "CAST_DIRECT_CHUNK_LOG", "max_grid": "CAST_MAX_GRID", "use_diag": "CAST_USE_DIAG",
            "mfma_min_d": "CAST_MFMA_MIN_D", "mfma_grid_per_cu": "CAST_MFMA_GRID_PER_CU",
            "mfma_direct_min_q": "CAST_MFMA_DIRECT_MIN_Q", "diag_unroll": "CAST_DIAG_UNROLL",
            "diag_max_grid": "CAST_DIAG_MAX_GRID", "diag_lds_table": "CAST_DIAG_LDS_TABLE",

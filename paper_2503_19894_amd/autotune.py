@@ -41,6 +41,7 @@ KNOB_CHOICES = [
     ("diag_order", [0, 1]),
     ("mfma_3m_min_d", [4, 5, 6, 7]),
     ("mfma_low_tile", [0, 1]),
+    ("direct_chunk_log", [6, 8, 10, 12]),
 ]
 
 

@@ -36,6 +36,7 @@ Tuning &tuning() {
         env("CAST_TILE_BITS", x.tile_bits);
         env("CAST_DIRECT_IPT", x.direct_ipt);
         env("CAST_DIRECT_NT", x.direct_nt);
+        env("CAST_DIRECT_CHUNK_LOG", x.direct_chunk_log);
         env("CAST_MAX_GRID", x.max_grid);
         env("CAST_USE_DIAG", x.use_diag);
         env("CAST_DIAG_UNROLL", x.diag_unroll);
@@ -395,6 +396,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "tile_bits") { *lo = 10; *hi = 13; return &t.tile_bits[i]; }
     if (key == "direct_ipt") { *lo = 1; *hi = 4; return &t.direct_ipt[i]; }
     if (key == "direct_nt") { *hi = 1; return &t.direct_nt[i]; }
+    if (key == "direct_chunk_log") { *lo = 6; *hi = 16; return &t.direct_chunk_log[i]; }
     if (key == "max_grid") { *lo = 256; return &t.max_grid[i]; }
     if (key == "use_diag") { *hi = 1; return &t.use_diag[i]; }
     if (key == "diag_unroll") { *lo = 1; *hi = 8; return &t.diag_unroll[i]; }

@@ -93,18 +93,18 @@ __device__ __forceinline__ void st(V *p, const V &v) {
     }
 }
 
-// Item i of a block-decomposed pass: items are cut into 64-item slices (one
-// wave each, 64 consecutive groups) and the block slot varies fastest across
-// slices, so the blocks of the same groups are processed close together in
-// time.  Their amplitudes often share cache lines (always when a target is
-// below the line size), and a block-slowest order would stream the state from
-// HBM once per block.  Needs ngroups to be a multiple of 64; the slice count
-// stays below 2^28 for n <= 34.
-__device__ __forceinline__ void direct_item(uint64_t i, uint32_t nblk, uint32_t &bs, uint64_t &g) {
-    const uint32_t s = __builtin_amdgcn_readfirstlane((uint32_t)(i >> 6));
+// Item i of a block-decomposed pass: items are cut into runs of 2^cl
+// consecutive groups of one block (cl >= 6, so a wave's 64 lanes share a
+// block) and the block slot varies fastest across runs, so the blocks of the
+// same groups are processed close together in time rather than in one sweep
+// of the state per block.  Longer runs keep longer contiguous address ranges
+// per block.  Needs 2^cl to divide ngroups; the run count stays below 2^28 for
+// n <= 34.
+__device__ __forceinline__ void direct_item(uint64_t i, uint32_t nblk, int cl, uint32_t &bs, uint64_t &g) {
+    const uint32_t s = __builtin_amdgcn_readfirstlane((uint32_t)(i >> cl));
     const uint32_t gs = s / nblk;
     bs = s - gs * nblk;
-    g = ((uint64_t)gs << 6) | (i & 63);
+    g = ((uint64_t)gs << cl) | (i & ((1ull << cl) - 1));
 }
 
 template <int D, typename R, int IPT, bool NT>
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
             const uint64_t i = it * per_iter + (uint64_t)u * 256 + threadIdx.x;
             uint32_t bs;
             uint64_t g;
-            direct_item(i, a.nblk, bs, g);
+            direct_item(i, a.nblk, a.chunk_log, bs, g);
             const uint32_t bid = a.blk[bs];
             uint64_t b = deposit(g, a.lowmask, a.k);
             for (int j = 0; j < a.k - D; ++j)
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
     for (uint64_t i = nfull * per_iter + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += stride) {
         uint32_t bs;
         uint64_t g;
-        direct_item(i, a.nblk, bs, g);
+        direct_item(i, a.nblk, a.chunk_log, bs, g);
         const uint32_t bid = a.blk[bs];
         uint64_t b = deposit(g, a.lowmask, a.k);
         for (int j = 0; j < a.k - D; ++j)
@@ -868,7 +868,6 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
     hipError_t e;
     if (kind == 4 || kind == 5) {
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
-        a.log_ngroups = n - k;
         a.ngroups = 1ull << (n - k);
         size_t lds = mfma_mat_bytes(dt, p);
         uint64_t grid;
@@ -957,9 +956,10 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         else e = launch_diag<float>(U, tu.diag_lds_table[dt] != 0, (float *)psi, (const float *)dmat, g, (int)grid, stream);
     } else if (direct) {
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
-        a.log_ngroups = n - k;
         a.ngroups = 1ull << (n - k);
-        // ngroups >= 64 (n - k >= 6): a 64-item slice is 64 consecutive groups of one block
+        // ngroups >= 64 (n - k >= 6), so a run of 2^chunk_log items is one block's groups
+        a.chunk_log = tu.direct_chunk_log[dt] < 6 ? 6 : tu.direct_chunk_log[dt];
+        if (a.chunk_log > n - k) a.chunk_log = n - k;
         if (dt == CAST_C128)
             e = launch_direct<double>(D, dt, (double *)psi, (const double *)dmat, a, stream);
         else

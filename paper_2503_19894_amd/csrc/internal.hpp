@@ -69,6 +69,7 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int tile_bits[3] = {0, 12, 12};  // LDS tile size log2(amplitudes)
     int direct_ipt[3] = {0, 4, 4};   // work items per thread per iteration (capped by registers)
     int direct_nt[3] = {0, 1, 1};    // non-temporal loads/stores in the direct kernel
+    int direct_chunk_log[3] = {0, 8, 8};  // direct kernel: log2(groups per block run), 6..16
     int max_grid[3] = {0, 1 << 20, 1 << 20};
     int use_diag[3] = {0, 1, 1};     // elementwise kernel for diagonal passes
     int diag_unroll[3] = {0, 4, 4};  // diagonal kernel: 16-byte chunks per thread per iteration

@@ -15,7 +15,7 @@ struct PassArgs {
     uint32_t blk[64];       // active block ids
     uint32_t nblk;
     int k;
-    int log_ngroups;
+    int chunk_log;          // direct: log2(items per block run), 6 <= chunk_log <= n - k
     int tb;                 // tile: log2(amplitudes per tile)
     int W;                  // tile: contiguous window bits
     int khi, klo;           // tile: targets at/above and below W

@@ -16,8 +16,8 @@ if not torch.cuda.is_available():
 
 import oracle  # noqa: E402
 import paper_2503_19894_amd as cast  # noqa: E402
-from circuits import (Gate, PauliTerm, dense_haar_layers, gate_sweep, hea_vqa, qft, random_state,  # noqa: E402
-                      rqc_u3_cx, tfim_fields, tfim_trotter, vqa_hamiltonian, vqa_thetas)
+from circuits import (Gate, PauliTerm, dense_haar_layers, gate_sweep, haar_unitary, hea_vqa, qft,  # noqa: E402
+                      random_state, rqc_u3_cx, tfim_fields, tfim_trotter, vqa_hamiltonian, vqa_thetas)
 
 TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
 DTYPES = [torch.complex128, torch.complex64]
@@ -128,6 +128,37 @@ def test_fused_circuits(dtype, case, k_max):
     got, fc = run_gpu(n, gates, psi0, dtype, k_max)
     err = maxerr(got, want)
     note(f"  passes={len(fc)} err={err:.2e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("chunk_log", [6, 8, 16])
+def test_direct_block_runs(dtype, chunk_log):
+    """Direct-kernel passes of gates with several blocks (d = 1, 2, 3 on
+    targets at bit 4 and above) under every block-run length, including
+    runs clamped to the group count, against the oracle."""
+    n = 17
+    rng = np.random.default_rng(21)
+    gates = []
+    for qs, d in (((4, 6, 9, 12, 16), 1), ((5, 7, 8, 15), 2), ((4, 10, 11, 13, 14, 16), 3)):
+        k = len(qs)
+        u = haar_unitary(1 << d, rng)
+        ph = np.exp(1j * rng.uniform(0.1, 6.0, 1 << (k - d)))
+        gates.append(Gate("unitary", qs, matrix=np.kron(np.diag(ph), u)))
+    psi0 = random_state(n, seed=5, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    old = cast.get_tuning("direct_chunk_log", dtype)
+    cast.set_tuning("direct_chunk_log", chunk_log, dtype)
+    try:
+        fc = cast.FusedCircuit(n, gates, k_max=1)
+        info = [(fc.gate(i)["d"], fc.gate(i)["active_blocks"], fc.pass_info(i, dtype)["kernel"]) for i in range(len(fc))]
+        sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+        sv.apply_circuit(fc)
+        err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    finally:
+        cast.set_tuning("direct_chunk_log", old, dtype)
+    note(f"direct block runs 2^{chunk_log} {dtype}: (d, blocks, kernel) {info} err {err:.2e}")
+    assert info == [(1, 16, 0), (2, 4, 0), (3, 8, 0)]
     assert err <= TOL[dtype]
 
 
