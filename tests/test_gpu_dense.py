@@ -38,8 +38,8 @@ def test_dense_haar_22_vs_oracle(dtype, tol):
 def test_dense_mfma_product_forms(dtype, tol, m3_min_d):
     """The matrix-core passes with the three-multiplication complex product
     at every block size (d >= 4) and with the four-product form only, on
-    direct and LDS-tile placements (a low target sends complex64 to the tile
-    kernel), against the oracle."""
+    direct and LDS-tile placements (the 4-qubit gate on 0, 2, 5, 9 goes to
+    the tile kernel), against the oracle."""
     n = 16
     gates = dense_haar_layers(n, depth=2, seed=3)
     gates.append(Gate("unitary", (0, 2, 5, 9), matrix=_haar(16, 5)))
