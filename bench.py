@@ -7,9 +7,12 @@ host fusion with k_max = 5.  One step = one application of the whole fused
 circuit (every fused gate = one in-place pass over the 2^30 amplitudes), with
 the state already resident in HBM.
 
-Headline value: effective HBM GB/s per fused-gate pass = passes x 2 x 2^30 x
-(amplitude bytes) / wall time of the timed steps (every amplitude read and
-written once per pass).  The line also carries:
+Headline value: effective HBM GB/s per fused-gate pass = the passes'
+algorithmic bytes (every amplitude of a non-identity block read and written
+once; amplitudes whose phase is 1 in a diagonal pass are not counted) summed
+over the fused list / wall time of the timed steps.  The dense-equivalent rate
+(every pass counted as a full read and write of the state) is reported as
+extras.c128.dense_equivalent_gbs.  The line also carries:
   roofline     -- the dominant kernel's algorithmic bytes (amplitudes of
                   non-identity blocks, read + written) over its average launch
                   duration from HIP events on the state's stream, vs 8 TB/s;
@@ -91,7 +94,9 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     wall = time.perf_counter() - t0
     per_pass /= steps
     state_bytes = (1 << n) * amp
-    eff_gbs = npass * 2 * state_bytes * steps / wall / 1e9
+    alg_bytes_per_step = float(sum(i["alg_bytes"] for i in infos))
+    alg_gbs = alg_bytes_per_step * steps / wall / 1e9
+    dense_equiv_gbs = npass * 2 * state_bytes * steps / wall / 1e9
     # per-kernel totals from the HIP events
     kern = {}
     for inf, ms in zip(infos, per_pass):
@@ -111,7 +116,8 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     dominant = max(kern, key=lambda x: kern[x]["ms_per_step"])
     out = {
         "passes": npass, "host_fusion_ms": round(host_fusion_ms, 2), "wall_s": wall,
-        "ms_per_step": wall / steps * 1e3, "effective_gbs": eff_gbs,
+        "ms_per_step": wall / steps * 1e3, "alg_bytes_per_step": alg_bytes_per_step, "alg_gbs": alg_gbs,
+        "dense_equivalent_gbs": dense_equiv_gbs,
         "paper_gibps_per_pass": state_bytes / (per_pass.sum() / npass * 1e-3) / 2**30,
         "event_ms_per_step": float(per_pass.sum()),
         "kernels": kern, "dominant": dominant,
@@ -120,6 +126,30 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     del sv, psi
     torch.cuda.empty_cache()
     return out
+
+
+def qft_c64_error(n, k_max, seed=5):
+    """Largest amplitude difference between the complex64 and the complex128
+    result of the fused QFT on the same input (the complex128 input rounded
+    to complex64), and the complex128 result's own norm error."""
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import qft, random_state_torch
+
+    fc = cast.FusedCircuit(n, qft(n), k_max=k_max)
+    a = random_state_torch(n, seed=seed, device="cuda", dtype=torch.complex128)
+    b = a.to(torch.complex64)
+    cast.StateVector(n, tensor=a).apply_circuit(fc)
+    cast.StateVector(n, tensor=b).apply_circuit(fc)
+    torch.cuda.synchronize()
+    err, chunk = 0.0, 1 << 26
+    for s in range(0, a.numel(), chunk):
+        err = max(err, float((b[s:s + chunk].to(torch.complex128) - a[s:s + chunk]).abs().max()))
+    nrm = float(torch.linalg.vector_norm(a))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"c64_max_abs_diff_vs_c128": err, "c128_norm_error": abs(nrm - 1.0)}
 
 
 def copy_bandwidth(gib=4, reps=5):
@@ -412,9 +442,12 @@ def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_ch
                 e, g = b.run(list(th))
             wall = time.perf_counter() - t0
             info = b.info()
+            tr = b.traffic()
             res[mname] = {"grads_per_s": sets * steps / wall, "s_per_batch": wall / steps,
                           "create_s": round(create_s, 3), "steps": info["steps"],
-                          "state_bytes": info["state_bytes"]}
+                          "state_bytes": info["state_bytes"], "alg_bytes_per_batch": tr["alg_bytes"],
+                          "state_passes_per_batch": tr["state_passes"],
+                          "alg_gbs": tr["alg_bytes"] / (wall / steps) / 1e9}
             del b
             torch.cuda.empty_cache()
         init = cast.StateVector(n, dtype=dtype)
@@ -446,7 +479,28 @@ def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_ch
     return out
 
 
-def cpu_baseline(n, target_s=15.0, max_gates=8):
+def vqa_summary(vqa):
+    """Headline figures of the batched VQA measurement: grads/s batched (best
+    mode) and plain, both dtypes, and the batched run's roofline: algorithmic
+    bytes of one batch (from the batch plan) over its time, against 8 TB/s."""
+    out = {}
+    for d in ("c128", "c64"):
+        r = vqa[d]
+        mode = max(("graph", "persistent"), key=lambda m: r[m]["grads_per_s"])
+        best = r[mode]
+        out[f"batched_{d}"] = round(best["grads_per_s"], 2)
+        out[f"plain_{d}"] = round(r["plain"]["grads_per_s"], 2)
+        out[f"roofline_{d}"] = {"bound": "hbm", "mode": mode, "achieved": round(best["alg_gbs"], 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(best["alg_gbs"] / HBM_PEAK_GBS, 4),
+                                "alg_bytes_per_grad": best["alg_bytes_per_batch"] / vqa["sets"],
+                                "state_passes_per_batch": best["state_passes_per_batch"]}
+    if "error_vs_fp64" in vqa["c64"]:
+        out["c64_error_vs_fp64"] = vqa["c64"]["error_vs_fp64"]
+    return out
+
+
+def cpu_baseline(n, target_s=15.0, max_gates=8, one_core=True):
     """The oracle (FP64, OpenMP over groups) on the first unfused QFT gates of
     a 2^n state; returns effective GB/s per pass in the same convention."""
     import numpy as np
@@ -470,8 +524,35 @@ def cpu_baseline(n, target_s=15.0, max_gates=8):
         if t_total >= target_s:
             break
     gbs = done * 2 * N * 16 / t_total / 1e9
-    return {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} unfused QFT-{n} gates on a 2^{n} FP64 state, {t_total:.1f} s"}
+    del psi
+    out = {"value": gbs, "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {done} unfused QFT-{n} gates on a 2^{n} FP64 state, {t_total:.1f} s",
+           "host": host_description()}
+    if one_core:
+        # the same oracle in a child process limited to one OpenMP thread
+        import subprocess
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--n", str(n),
+                            "--cpu-target-s", "8", "--cpu-max-gates", "2"],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            out["one_core"] = {"value": one["value"], "sample": one["sample"]}
+    return out
+
+
+def host_description():
+    """CPU model, logical CPUs and memory of the host the oracle ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        mem = next(int(l.split()[1]) for l in open("/proc/meminfo") if l.startswith("MemTotal"))
+    except (OSError, StopIteration):
+        mem = 0
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_total_gib": round(mem / 2**20, 1)}
 
 
 TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -584,7 +665,14 @@ def main():
                     help="only the circuit-family table (fusion none / size-only / adaptive, per pass and "
                          "cache-blocked); prints one JSON object")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only the oracle's CPU baseline (no GPU); prints one JSON object")
+    ap.add_argument("--cpu-target-s", type=float, default=15.0)
+    ap.add_argument("--cpu-max-gates", type=int, default=8)
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.n, args.cpu_target_s, args.cpu_max_gates, one_core=False)), flush=True)
+        return
     if args.summarize_kernel_trace:
         print(summarize_kernel_trace(*args.summarize_kernel_trace))
         return
@@ -631,6 +719,8 @@ def main():
     if not args.no_c64:
         progress("qft complex64")
         extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup)
+    progress("qft complex64 error against complex128")
+    c64_err = None if args.no_c64 else qft_c64_error(args.n, args.k_max)
     dom = main_run["kernels"][main_run["dominant"]]
     traffic = recorded_traffic(main_run["dominant"])
     copy_gbs, copy_kind = copy_bandwidth()
@@ -654,7 +744,7 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.n)
     line = {
         "metric": "effective HBM GB/s per fused-gate pass at 30q",
-        "value": round(main_run["effective_gbs"], 1),
+        "value": round(main_run["alg_gbs"], 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -669,12 +759,9 @@ def main():
                    "k_max": args.k_max, "fused_passes": main_run["passes"],
                    "state_bytes": (1 << args.n) * 16},
         "roofline": roof,
+        "c64_error_vs_fp64": c64_err,
         "cpu_baseline": cpu,
-        "vqa_grads_per_s": None if vqa is None else {
-            "batched_c128": round(max(vqa["c128"]["graph"]["grads_per_s"], vqa["c128"]["persistent"]["grads_per_s"]), 2),
-            "plain_c128": round(vqa["c128"]["plain"]["grads_per_s"], 2),
-            "batched_c64": round(max(vqa["c64"]["graph"]["grads_per_s"], vqa["c64"]["persistent"]["grads_per_s"]), 2),
-            "plain_c64": round(vqa["c64"]["plain"]["grads_per_s"], 2)},
+        "vqa_grads_per_s": None if vqa is None else vqa_summary(vqa),
         "blocked": {d: {"ms_per_step": round(r["blocked"]["ms_per_step"], 3), "hbm_passes": r["blocked"]["hbm_passes"],
                         "speedup_vs_per_pass": round(r["blocked"]["speedup_vs_per_pass"], 3)}
                     for d, r in (("c128", main_run), ("c64", extras.get("c64"))) if r},

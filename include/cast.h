@@ -258,7 +258,11 @@ void fused_destroy(cast_fused *f);
  * complex products with three real products instead of four; 4..7, 7 = never),
  * "mfma_low_tile" (1: a matrix-core pass with d <= 4 and a target below bit 4
  * runs on the LDS tile when at most one target lies above the tile's
- * contiguous window or the gate has several blocks; 0: the direct gather).
+ * contiguous window or the gate has several blocks; 0: the direct gather),
+ * "persistent_spin_limit" (polls a persistent batch item makes before its
+ * dependency wait gives up and the run fails with CAST_EHIP; read by
+ * batch_create; 0 makes every item that has a dependency fail at once, which
+ * exercises that error path from the host).
  * CAST_EINVAL for an unknown key or an out-of-range value.  Not thread-safe
  * against concurrent launches: set knobs before queuing work. */
 cast_status tuning_set(const char *key, cast_dtype dt, int value);
@@ -340,6 +344,15 @@ cast_status batch_run(cast_batch *b, const double *const *theta, double *energie
 /* Global steps, total work items of the persistent launch, and bytes of the
  * batch's device states (psi and lambda of every instance). */
 cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items, double *state_bytes);
+
+/* Algorithmic HBM bytes of one batch_run as planned: every instance's
+ * initial state written once (2^n amplitudes), each forward segment reading
+ * and writing psi, the lambda = H psi op reading psi and writing lambda, and
+ * each reverse segment reading and writing both psi and lambda.  Matrices,
+ * partial sums and results are not counted.  *state_passes receives the
+ * number of whole-state read+write passes those ops make (reverse segments
+ * count two).  Either output may be NULL. */
+cast_status batch_traffic(const cast_batch *b, double *alg_bytes, uint64_t *state_passes);
 
 void batch_destroy(cast_batch *b);
 

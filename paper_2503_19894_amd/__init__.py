@@ -93,6 +93,7 @@ SIGNATURES = {
     "batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_c_double_p), _c_double_p,
                                  ctypes.POINTER(_c_double_p)]),
     "batch_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_uint64), _c_double_p]),
+    "batch_traffic": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_uint64)]),
     "batch_destroy": (None, [ctypes.c_void_p]),
     "tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]),
     "tuning_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _c_int_p]),
@@ -462,6 +463,12 @@ class Batch:
         batch_info(self.handle, ctypes.byref(ns), ctypes.byref(items), ctypes.byref(sb))
         return {"steps": ns.value, "items": items.value, "state_bytes": sb.value}
 
+    def traffic(self):
+        """Algorithmic HBM bytes of one run and its whole-state passes."""
+        ab, sp = ctypes.c_double(), ctypes.c_uint64()
+        batch_traffic(self.handle, ctypes.byref(ab), ctypes.byref(sp))
+        return {"alg_bytes": ab.value, "state_passes": sp.value}
+
     def run(self, thetas):
         """thetas[i]: n_params[i] angles.  Returns (energies [B], grads list)."""
         th = [np.ascontiguousarray(t, dtype=np.float64).reshape(-1) for t in thetas]
@@ -500,13 +507,15 @@ class CircuitEnergy(torch.autograd.Function):
                 e, g = adjoint(init, gates, row, terms)
                 es.append(e)
                 gs.append(g)
-        ctx.save_for_backward(torch.tensor(np.array(gs), dtype=theta.dtype).reshape(theta.shape))
+        # the gradient lives where theta lives, so autograd gets it back on
+        # theta's device whatever that is
+        ctx.save_for_backward(torch.tensor(np.array(gs), dtype=theta.dtype).reshape(theta.shape).to(theta.device))
         return torch.tensor(np.asarray(es), dtype=theta.dtype).reshape(theta.shape[:-1]).to(theta.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         (g,) = ctx.saved_tensors
-        return grad_out.to(g.device).unsqueeze(-1) * g, None, None, None, None
+        return grad_out.unsqueeze(-1).to(g.device) * g, None, None, None, None
 
 
 apply_tuning_file()

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <mutex>
 
 #include "internal.hpp"
@@ -189,45 +190,61 @@ cast_status upload_plan(const PassPlan &p, cast_dtype dt, DeviceMatrix *out) {
     return upload_plans(std::vector<PassPlan>{p}, dt, out, &off);
 }
 
-// Small per-thread cache of matrix buffers for apply_gate: a buffer is reused
-// only after the stream that used it has passed an event recorded after use.
+// Matrix buffers for apply_gate, shared by all host threads.  A slot is
+// claimed under the lock (busy) and stays claimed until apply_gate has
+// recorded its completion event after the launch that reads it; only then
+// can another call take it, and only once the stream has passed that event.
+// The copy itself runs outside the lock.  std::deque keeps slot addresses
+// valid while new slots are appended.
 struct Staging {
     void *ptr = nullptr;
     size_t bytes = 0;
     hipEvent_t done = nullptr;
+    bool busy = false;
 };
 static std::mutex g_stage_mu;
-static std::vector<Staging> g_stage;
+static std::deque<Staging> g_stage;
 
-static cast_status stage_matrix(const PassPlan &p, cast_dtype dt, hipStream_t s, void **dptr,
-                                hipEvent_t *ev) {
+static void release_slot(Staging *slot) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    slot->busy = false;
+}
+
+static cast_status stage_matrix(const PassPlan &p, cast_dtype dt, hipStream_t s, Staging **out) {
     std::vector<double> hd;
     std::vector<float> hf;
     size_t bytes;
     const void *src;
     if (dt == CAST_C128) { pack<double>(p, hd); bytes = hd.size() * 8; src = hd.data(); }
     else { pack<float>(p, hf); bytes = hf.size() * 4; src = hf.data(); }
-    std::lock_guard<std::mutex> lk(g_stage_mu);
     Staging *slot = nullptr;
-    for (Staging &st : g_stage)
-        if (st.bytes >= bytes && hipEventQuery(st.done) == hipSuccess) { slot = &st; break; }
-    if (!slot) {
-        Staging st;
-        st.bytes = std::max<size_t>(bytes, 4096);
-        cast_status rc = dev_alloc(&st.ptr, st.bytes);
-        if (rc) return rc;
-        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
-            dev_free(st.ptr);
-            return fail(CAST_EHIP, "hipEventCreate failed");
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        for (Staging &st : g_stage)
+            if (!st.busy && st.bytes >= bytes && hipEventQuery(st.done) == hipSuccess) { slot = &st; break; }
+        if (!slot) {
+            Staging st;
+            st.bytes = std::max<size_t>(bytes, 4096);
+            cast_status rc = dev_alloc(&st.ptr, st.bytes);
+            if (rc) return rc;
+            if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+                dev_free(st.ptr);
+                return fail(CAST_EHIP, "hipEventCreate failed");
+            }
+            g_stage.push_back(st);
+            slot = &g_stage.back();
         }
-        g_stage.push_back(st);
-        slot = &g_stage.back();
+        slot->busy = true;
     }
-    // stream-ordered copy from pageable memory completes the host read before returning
-    CAST_HIP_TRY(hipMemcpyAsync(slot->ptr, src, bytes, hipMemcpyHostToDevice, s));
-    CAST_HIP_TRY(hipStreamSynchronize(s));
-    *dptr = slot->ptr;
-    *ev = slot->done;
+    // stream-ordered copy from pageable memory; the synchronisation makes the
+    // host buffer's lifetime irrelevant
+    hipError_t e = hipMemcpyAsync(slot->ptr, src, bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release_slot(slot);
+        return fail(CAST_EHIP, std::string("matrix staging: ") + hipGetErrorString(e));
+    }
+    *out = slot;
     return CAST_OK;
 }
 
@@ -366,11 +383,12 @@ cast_status apply_gate(cast_sv *sv, const int *qubits, int k, const double *matr
     PassPlan p;
     if (cast_status rc = make_plan(k, qubits, m.data(), 1e-14, 1e-14, &p)) return rc;
     if (p.identity()) return CAST_OK;
-    void *dmat = nullptr;
-    hipEvent_t ev = nullptr;
-    if (cast_status rc = stage_matrix(p, sv->dt, sv->stream, &dmat, &ev)) return rc;
-    cast_status rc = launch_pass(sv->data, sv->n, sv->dt, p, dmat, sv->stream);
-    CAST_HIP_TRY(hipEventRecord(ev, sv->stream));
+    Staging *slot = nullptr;
+    if (cast_status rc = stage_matrix(p, sv->dt, sv->stream, &slot)) return rc;
+    cast_status rc = launch_pass(sv->data, sv->n, sv->dt, p, slot->ptr, sv->stream);
+    // a slot whose event could not be recorded is never handed out again
+    CAST_HIP_TRY(hipEventRecord(slot->done, sv->stream));
+    release_slot(slot);
     return rc;
 }
 
@@ -410,6 +428,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "mfma_3m_min_d") { *lo = 4; *hi = 7; return &t.mfma_3m_min_d[i]; }
     if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 13 : 12; return &t.blocked_tile_bits[i]; }
     if (key == "blocked_threads") { *lo = 256; *hi = 1024; return &t.blocked_threads[i]; }
+    if (key == "persistent_spin_limit") return &t.persistent_spin_limit[i];
     return nullptr;
 }
 

@@ -77,6 +77,7 @@ struct cast_batch {
     hipGraphExec_t exec = nullptr;
     int persistent_grid = 1024;
     uint32_t persistent_chunk = 16;
+    uint32_t spin_limit = 1u << 24;
 };
 
 namespace cast {
@@ -152,7 +153,7 @@ static cast_status queue_program(cast_batch *b) {
     if (b->mode == 2) {
         if (cast_status rc = batch_zero(b->d_counters, 2 + (size_t)b->ninst, s)) return rc;
         if (cast_status rc = batch_launch_persistent(b->dev, b->dt, b->total_items, b->persistent_grid,
-                                                     b->d_counters, 1u << 24, b->persistent_chunk, b->lds_bytes, s))
+                                                     b->d_counters, b->spin_limit, b->persistent_chunk, b->lds_bytes, s))
             return rc;
     } else {
         for (int st = 0; st < b->nsteps; ++st)
@@ -605,6 +606,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     b->persistent_grid = cus * 4;
+    b->spin_limit = (uint32_t)tuning().persistent_spin_limit[dt == CAST_C64 ? CAST_C64 : CAST_C128];
     if (const char *e = std::getenv("CAST_PERSISTENT_WG_PER_CU")) b->persistent_grid = cus * std::max(1, atoi(e));
     if (const char *e = std::getenv("CAST_PERSISTENT_CHUNK")) b->persistent_chunk = (uint32_t)std::max(1, atoi(e));
     if (mode >= 1) {
@@ -701,6 +703,28 @@ cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items,
         for (auto &ip : b->inst) s += 2.0 * std::ldexp(1.0, ip.n) * (double)amp_bytes(b->dt);
         *state_bytes = s;
     }
+    return CAST_OK;
+}
+
+cast_status batch_traffic(const cast_batch *b, double *alg_bytes, uint64_t *state_passes) {
+    if (!b) return fail(CAST_EINVAL, "batch is NULL");
+    double bytes = 0;
+    uint64_t passes = 0;
+    for (auto &ip : b->inst) {
+        const double S = std::ldexp(1.0, ip.n) * (double)amp_bytes(b->dt);
+        bytes += S;                           // initial state written
+        for (auto &op : ip.ops) {
+            if (op.kind == BK_ADJ) {          // psi and lambda read and written
+                bytes += 4 * S;
+                passes += 2;
+            } else {                          // FWD: psi read and written; HPSI: psi read, lambda written
+                bytes += 2 * S;
+                passes += 1;
+            }
+        }
+    }
+    if (alg_bytes) *alg_bytes = bytes;
+    if (state_passes) *state_passes = passes;
     return CAST_OK;
 }
 

@@ -525,14 +525,17 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
                     pend = 0;
                 }
                 // poll with relaxed loads (an acquire per poll would invalidate the
-                // caches under every other workgroup), then acquire once
-                if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
+                // caches under every other workgroup), then acquire once.  A
+                // spin limit of 0 fails every item that has a dependency at all,
+                // so the error path can be forced from the host.
+                const bool force = spin_limit == 0 && rec.need != 0;
+                if (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
                     if (pend) {
                         __hip_atomic_fetch_add(done, pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         pend = 0;
                     }
                     uint32_t spins = 0;
-                    while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
+                    while (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
                         if (++spins > spin_limit ||
                             __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             atomicExch(&counters[1], 1ull);

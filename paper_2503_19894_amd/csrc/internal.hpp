@@ -83,6 +83,9 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int mfma_3m_min_d[3] = {0, 6, 6};  // matrix cores: three-multiplication complex product from this d (7: never)
     int blocked_tile_bits[3] = {0, 13, 12};  // cache-blocked passes: log2(amplitudes per LDS tile)
     int blocked_threads[3] = {0, 512, 512};  // cache-blocked passes: threads per workgroup (256, 512, 1024)
+    // persistent batch launch: polls before a dependency wait gives up; 0
+    // makes every dependency fail at once (exercises the error path)
+    int persistent_spin_limit[3] = {0, 1 << 24, 1 << 24};
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).

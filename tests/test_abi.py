@@ -140,3 +140,41 @@ def test_blocked_entry_points_validation():
                                        None, None) == EINVAL
     assert cast._lib.blocked_pass_info(fc.handle, 14, cast.C128, 0, None, None, None, None, None) == 0
     assert cast._lib.apply_circuit_blocked(None, fc.handle) == EINVAL
+
+
+def test_library_gate_table_matches_oracle_gates():
+    """Every name of the library's gate table against the oracle's own gate
+    definitions (two independent implementations), at random angles."""
+    import oracle
+    from circuits import Gate
+    rng = np.random.default_rng(5)
+    arity = {"cx": 2, "cz": 2, "cp": 2, "swap": 2, "rxx": 2, "ryy": 2, "rzz": 2}
+    nparams = {"p": 1, "u3": 3, "rx": 1, "ry": 1, "rz": 1, "rxx": 1, "ryy": 1, "rzz": 1, "cp": 1}
+    for name in ("id h x y z s t p u3 rx ry rz rxx ryy rzz cx cz cp swap").split():
+        for _ in range(3):
+            params = tuple(float(x) for x in rng.uniform(-2 * np.pi, 2 * np.pi, nparams.get(name, 0)))
+            m = cast.std_matrix(name, params)
+            lib = m[..., 0] + 1j * m[..., 1]
+            want = oracle.gates.matrix(Gate(name, tuple(range(arity.get(name, 1))), params))
+            assert lib.shape == want.shape, name
+            np.testing.assert_allclose(lib, want, atol=1e-15, err_msg=name)
+
+
+def test_device_byte_cap_gives_enomem():
+    """CAST_MAX_DEVICE_BYTES caps what the library allocates: a state larger
+    than the cap fails with CAST_ENOMEM before any device call (so this runs
+    without a GPU), with the cap named in the message."""
+    import subprocess
+    import sys
+    code = ("import ctypes, paper_2503_19894_amd as c\n"
+            "h = ctypes.c_void_p()\n"
+            "try:\n"
+            "    c.sv_create(20, c.C128, None, ctypes.byref(h))\n"
+            "    print('created')\n"
+            "except c.CastError as e:\n"
+            "    print(e.code, c.last_error())\n")
+    env = dict(os.environ, CAST_MAX_DEVICE_BYTES=str(1 << 20))
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    out = r.stdout.strip().splitlines()[-1]
+    assert out.startswith("-2 ") and "CAST_MAX_DEVICE_BYTES" in out, out

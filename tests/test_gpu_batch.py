@@ -133,3 +133,32 @@ def test_two_qubit_generators_unsorted_and_high_qubits(dtype):
             ew, gw = oracle.adjoint_grad(n, gates, thetas[i], H)
             assert abs(e[i] - ew) <= tol, (mode, i)
             assert np.max(np.abs(g[i] - gw)) <= tol, (mode, i, np.max(np.abs(g[i] - gw)))
+
+
+def test_persistent_wait_bound_error_path():
+    """The persistent launch's bounded dependency wait, forced to give up from
+    the host (spin limit 0: every item with a dependency fails at once): the
+    run returns CAST_EHIP with its message, every workgroup exits, and a batch
+    built afterwards with the normal limit runs and matches the oracle."""
+    n = 6
+    gates, P, th, H = vqa_case(n, layers=2, sets=3, seed=5)
+    B = th.shape[0]
+    dt = torch.complex128
+    old = cast.get_tuning("persistent_spin_limit", dt)
+    cast.set_tuning("persistent_spin_limit", 0, dt)
+    try:
+        b = cast.Batch([gates] * B, [n] * B, [P] * B, [H] * B, dtype=dt, mode=cast.BATCH_PERSISTENT_GRAPH)
+        with pytest.raises(cast.CastError) as ei:
+            b.run(list(th))
+        print(f"forced wait failure: code {ei.value.code}, {cast.last_error()}", flush=True)
+        assert ei.value.code == -3 and "exceeded its bound" in cast.last_error()
+        del b
+    finally:
+        cast.set_tuning("persistent_spin_limit", old, dt)
+    torch.cuda.synchronize()
+    b = cast.Batch([gates] * B, [n] * B, [P] * B, [H] * B, dtype=dt, mode=cast.BATCH_PERSISTENT_GRAPH)
+    e, g = b.run(list(th))
+    for i in range(B):
+        ew, gw = oracle.adjoint_grad(n, gates, th[i], H)
+        assert abs(e[i] - ew) <= TOL[dt]
+        assert np.max(np.abs(g[i] - gw)) <= TOL[dt]

@@ -3,8 +3,9 @@ in the launch configuration bench.py times.
 
 The full state is far too large for the oracle's replay, so the checks are
 (1) sampled outputs against the DFT closed form (a property of the QFT at any
-size, pinned against numpy.fft in tests/test_dft_helper.py) and (2) the fused
-inverse QFT returning the input, amplitude by amplitude."""
+size, pinned against numpy.fft in tests/test_dft_helper.py), (2) the fused
+inverse QFT returning the input, amplitude by amplitude, and (3) the whole
+output state against sqrt(N) times a library inverse FFT of the input."""
 import math
 import sys
 
@@ -60,3 +61,30 @@ def test_qft30_closed_form_and_inverse(dtype, tol, mode):
     assert err <= tol
     nrm = float(torch.linalg.vector_norm(psi.to(torch.complex128)))
     assert abs(nrm - 1.0) <= tol
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("mode", ["per_pass", "blocked"])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
+def test_qft30_full_state_vs_fft(dtype, tol, mode):
+    """Every one of the 2^30 outputs against the DFT closed form: with the gate
+    order used here the QFT maps psi to sqrt(N) * ifft(psi) (a library FFT,
+    independent of this library), evaluated in FP64 on the device."""
+    n = N_QUBITS
+    N = 1 << n
+    print(f"qft{n} full state {dtype} {mode}: input and FP64 FFT", flush=True)
+    psi = random_state_torch(n, seed=3, device="cuda", dtype=dtype)
+    ref = torch.fft.ifft(psi.to(torch.complex128))
+    ref.mul_(math.sqrt(N))
+    torch.cuda.synchronize()
+    sv = cast.StateVector(n, tensor=psi)
+    fc = cast.FusedCircuit(n, qft(n), k_max=5)
+    print(f"  {len(fc)} fused gates; applying", flush=True)
+    (sv.apply_circuit if mode == "per_pass" else sv.apply_circuit_blocked)(fc)
+    torch.cuda.synchronize()
+    err = 0.0
+    chunk = 1 << 26
+    for s in range(0, N, chunk):
+        err = max(err, float((psi[s:s + chunk].to(torch.complex128) - ref[s:s + chunk]).abs().max()))
+    print(f"  max |d amp| over all {N} outputs: {err:.2e}", flush=True)
+    assert err <= tol

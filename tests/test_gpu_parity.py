@@ -3,6 +3,7 @@ element by element, on the same seeded inputs.
 
 Bars: max |d amp| <= 1e-12 for complex128 and <= 1e-5 for complex64."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -13,6 +14,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 import oracle  # noqa: E402
 import paper_2503_19894_amd as cast  # noqa: E402
@@ -61,7 +64,9 @@ def test_config1_apply_gate_one_by_one(dtype):
     want = oracle.run_circuit(n, gates)
     sv = cast.StateVector(n, dtype=dtype)
     for g in gates:
-        sv.apply_gate(g.qubits, oracle.gates.matrix(g))
+        # the library's own gate table, not the oracle's matrices
+        m = cast.std_matrix(g.name, g.params)
+        sv.apply_gate(g.qubits, m[..., 0] + 1j * m[..., 1])
     assert maxerr(sv.numpy(), want) <= TOL[dtype]
 
 
@@ -256,3 +261,92 @@ def test_autograd_function():
         e_want, g_want = oracle.adjoint_grad(n, gates, theta[b].detach().numpy(), H)
         assert abs(float(E[b]) - e_want) <= 1e-10
         np.testing.assert_allclose(theta.grad[b].numpy(), w[b].item() * g_want, atol=1e-10)
+
+
+@pytest.mark.parametrize("sets", [1, 3])
+def test_autograd_function_cuda_theta(sets):
+    """theta on the GPU: forward and backward keep every tensor on theta's
+    device, and theta.grad matches the oracle's adjoint gradient (one set:
+    the per-instance path; three sets: the batched program)."""
+    n = 6
+    gates, P = hea_vqa(n, 2)
+    H = vqa_hamiltonian(n)
+    th = vqa_thetas(P, sets, seed=4)
+    theta = torch.tensor(th if sets > 1 else th[0], device="cuda", requires_grad=True)
+    E = cast.CircuitEnergy.apply(theta, n, gates, H)
+    assert E.device == theta.device
+    w = torch.linspace(1.0, -1.0, max(sets, 1), dtype=torch.float64, device="cuda")[:sets]
+    (E * (w if sets > 1 else w[0])).sum().backward()
+    assert theta.grad.device == theta.device
+    grad = theta.grad.cpu().numpy().reshape(sets, P)
+    for b in range(sets):
+        e_want, g_want = oracle.adjoint_grad(n, gates, th[b], H)
+        got_e = float(E.reshape(-1)[b])
+        print(f"autograd cuda theta set {b}: dE {abs(got_e - e_want):.2e}", flush=True)
+        assert abs(got_e - e_want) <= 1e-10
+        np.testing.assert_allclose(grad[b], float(w[b]) * g_want, atol=1e-10)
+
+
+def test_apply_gate_concurrent_host_threads():
+    """Four host threads, each with its own stream and state, call apply_gate
+    at the same time (ctypes releases the GIL): the shared matrix staging
+    slots must never hand one thread's buffer to another while its pass is
+    pending.  Each state is checked against the oracle."""
+    import threading
+
+    n, T, G = 12, 4, 60
+    results = [None] * T
+    errors = []
+
+    def work(i):
+        try:
+            rng = np.random.default_rng(900 + i)
+            gates = []
+            for _ in range(G):
+                k = int(rng.integers(1, 4))
+                qs = tuple(int(q) for q in rng.permutation(n)[:k])
+                gates.append(Gate("unitary", qs, matrix=haar_unitary(1 << k, rng)))
+            psi0 = random_state(n, seed=i, workload=8)
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                sv = cast.StateVector(n, tensor=torch.tensor(psi0, device="cuda"))
+                for g in gates:
+                    sv.apply_gate(g.qubits, g.matrix)
+                results[i] = (gates, psi0, sv.numpy())
+        except Exception as e:  # reported below, on the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(T)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for i, (gates, psi0, got) in enumerate(results):
+        err = float(np.max(np.abs(got - oracle.run_circuit(n, gates, psi0))))
+        print(f"thread {i}: max |d amp| {err:.2e}", flush=True)
+        assert err <= 1e-12
+
+
+def test_device_byte_cap_accounting():
+    """With CAST_MAX_DEVICE_BYTES set (in a child process, since the cap is
+    read once), a second state that would exceed the cap fails with
+    CAST_ENOMEM, and freeing the first makes room again."""
+    import subprocess
+    code = ("import ctypes, paper_2503_19894_amd as c\n"
+            "a, b = ctypes.c_void_p(), ctypes.c_void_p()\n"
+            "c.sv_create(20, c.C128, None, ctypes.byref(a))\n"
+            "try:\n"
+            "    c.sv_create(20, c.C128, None, ctypes.byref(b))\n"
+            "    print('second created')\n"
+            "except c.CastError as e:\n"
+            "    print('second', e.code)\n"
+            "c.sv_destroy(a)\n"
+            "c.sv_create(20, c.C128, None, ctypes.byref(b))\n"
+            "c.sv_destroy(b)\n"
+            "print('third ok')\n")
+    env = dict(os.environ, CAST_MAX_DEVICE_BYTES=str(24 << 20))
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    print(r.stdout, r.stderr[-2000:], flush=True)
+    assert r.returncode == 0
+    assert "second -2" in r.stdout and "third ok" in r.stdout
