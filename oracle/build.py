@@ -16,5 +16,16 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(driver_src, out_dir):
+    """The oracle and a driver `driver_src` compiled together with
+    AddressSanitizer and UndefinedBehaviorSanitizer; returns the binary."""
+    os.makedirs(out_dir, exist_ok=True)
+    exe = os.path.join(out_dir, "oracle_driver")
+    subprocess.run(["gcc", "-O1", "-g", "-fno-fast-math", "-fopenmp", "-std=c99", "-Wall",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                    "-o", exe, os.path.join(HERE, "sv_oracle.c"), driver_src, "-lm"], check=True)
+    return exe
+
+
 if __name__ == "__main__":
     print(build())
