@@ -40,14 +40,18 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_label(info, dtype_name):
     """Name of the kernel template instance a pass launches, as the profiler
-    prints it (without the argument list), from the library's active knobs."""
+    prints it (without the argument list), from the library's active knobs.
+    `info` is a schedule entry (FusedCircuit.schedule) with the fused gate's
+    block dimension "d" added for single-gate passes."""
     import torch
 
     import paper_2503_19894_amd as cast
 
     dt = torch.complex128 if dtype_name == "c128" else torch.complex64
-    kind, d = info["kernel"], info["d"]
+    kind, d = info["kernel"], info.get("d", 0)
     r = "double" if dtype_name == "c128" else "float"
+    if kind == 6:
+        return f"k_diag_run<{r}, {cast.get_tuning('diag_run_unroll', dt)}, {info['tables']}>"
     if kind == 3:
         lds = "true" if cast.get_tuning("diag_lds_table", dt) else "false"
         return f"k_diag<{r}, {cast.get_tuning('diag_unroll', dt)}, {lds}>"
@@ -79,8 +83,8 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     t0 = time.perf_counter()
     fc = cast.FusedCircuit(n, gates, k_max=k_max)
     host_fusion_ms = (time.perf_counter() - t0) * 1e3
-    npass = len(fc)
-    infos = [fc.pass_info(i, dtype) for i in range(npass)]
+    infos = schedule_infos(fc, dtype)
+    npass = len(infos)
     psi = random_state_torch(n, seed=seed, device="cuda", dtype=dtype)
     sv = cast.StateVector(n, tensor=psi)
     for _ in range(warmup):
@@ -115,7 +119,8 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
         k["achieved_gbs"] = k["alg_bytes_per_step"] / (k["ms_per_step"] * 1e-3) / 1e9
     dominant = max(kern, key=lambda x: kern[x]["ms_per_step"])
     out = {
-        "passes": npass, "host_fusion_ms": round(host_fusion_ms, 2), "wall_s": wall,
+        "passes": npass, "fused_gates": len(fc), "diag_run_passes": sum(i["kernel"] == 6 for i in infos),
+        "host_fusion_ms": round(host_fusion_ms, 2), "wall_s": wall,
         "ms_per_step": wall / steps * 1e3, "alg_bytes_per_step": alg_bytes_per_step, "alg_gbs": alg_gbs,
         "dense_equivalent_gbs": dense_equiv_gbs,
         "paper_gibps_per_pass": state_bytes / (per_pass.sum() / npass * 1e-3) / 2**30,
@@ -126,6 +131,16 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     del sv, psi
     torch.cuda.empty_cache()
     return out
+
+
+def schedule_infos(fc, dtype):
+    """The passes apply_circuit makes (diagonal runs merged), each with the
+    block dimension of its fused gate for single-gate passes."""
+    infos = fc.schedule(dtype)
+    for inf in infos:
+        if inf["kernel"] != 6 and inf["kernel"] >= 0:
+            inf["d"] = fc.pass_info(inf["first"], dtype)["d"]
+    return infos
 
 
 def qft_c64_error(n, k_max, seed=5):
@@ -273,6 +288,65 @@ def run_jit():
     return out
 
 
+SWEEP_KINDS = ("haar", "diag", "x", "ctrl", "h", "u3")
+
+
+def sweep_targets(n, k, place, rng):
+    if place == "low":
+        return tuple(range(k))
+    if place == "high":
+        return tuple(range(n - k, n))
+    return tuple(int(q) for q in sorted(rng.permutation(n)[:k]))
+
+
+def run_sweep(ns=(28, 30), reps=5):
+    """Single fused-gate passes (the paper's single-gate table pattern,
+    widened): k = 1..6 x {dense Haar, diagonal, X^k, controlled-U, H^k, U3^k}
+    x targets {low, high, random} on 2^n states, both dtypes.  Each case is
+    fused with k_max = k into one gate; its pass time is the median of `reps`
+    HIP-event timings; the rate counts the pass's algorithmic bytes (every
+    amplitude of a non-identity block read and written once)."""
+    import numpy as np
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import gate_sweep, random_state_torch
+
+    rows = []
+    for dname, dt in (("c128", torch.complex128), ("c64", torch.complex64)):
+        for n in ns:
+            psi = random_state_torch(n, seed=4, device="cuda", dtype=dt)
+            sv = cast.StateVector(n, tensor=psi)
+            rng = np.random.default_rng(n)
+            for k in range(1, 7):
+                for kind in SWEEP_KINDS:
+                    if kind == "ctrl" and k == 1:
+                        continue
+                    for place in ("low", "high", "random"):
+                        qs = sweep_targets(n, k, place, rng)
+                        fc = cast.FusedCircuit(n, gate_sweep(kind, k, qs, seed=k), k_max=k)
+                        sched = schedule_infos(fc, dt)
+                        if len(sched) != 1:
+                            continue
+                        inf = sched[0]
+                        sv.apply_circuit(fc)
+                        t = float(np.median([sv.apply_circuit_timed(fc)[0] for _ in range(reps)]))
+                        gbs = inf["alg_bytes"] / (t * 1e-3) / 1e9
+                        tfl = inf["flops"] / (t * 1e-3) / 1e12
+                        peak_fl = 78.6 if dname == "c128" else 157.3
+                        rows.append({"dtype": dname, "n": n, "k": k, "kind": kind, "place": place,
+                                     "qubits": list(qs), "kernel": inf["kernel"], "d": inf.get("d", 0),
+                                     "ms": round(t, 4), "alg_gbs": round(gbs, 1),
+                                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "tflops": round(tfl, 2),
+                                     "frac_fp": round(tfl / peak_fl, 4)})
+                        print(f"[bench] sweep {dname} n={n} k={k} {kind} {place}: {t:.3f} ms "
+                              f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
+                        del fc
+            del sv, psi
+            torch.cuda.empty_cache()
+    return rows
+
+
 def run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, per_pass_ms):
     """The same fused circuit cache-blocked (several fused gates per HBM
     pass): HBM passes, time per step, the passes' HBM rate (every pass reads
@@ -327,14 +401,14 @@ def run_dense(n=32, depth=20, steps=1, warmup=1):
 
     gates = dense_haar_layers(n, depth, seed=0)
     fc = cast.FusedCircuit(n, gates, k_max=6)
-    infos = [fc.pass_info(i, torch.complex128) for i in range(len(fc))]
+    infos = schedule_infos(fc, torch.complex128)
     psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
     psi[0] = 1
     sv = cast.StateVector(n, tensor=psi)
     for _ in range(warmup):
         sv.apply_circuit(fc)
     torch.cuda.synchronize()
-    per = np.zeros(len(fc))
+    per = np.zeros(len(infos))
     t0 = time.perf_counter()
     for _ in range(steps):
         per += sv.apply_circuit_timed(fc)
@@ -342,6 +416,8 @@ def run_dense(n=32, depth=20, steps=1, warmup=1):
     per /= steps
     kern = {}
     for inf, ms in zip(infos, per):
+        if inf["kernel"] < 0:
+            continue
         lab = kernel_label(inf, "c128")
         k = kern.setdefault(lab, {"launches": 0, "ms": 0.0, "alg_bytes": 0.0, "flops": 0.0})
         k["launches"] += 1
@@ -665,6 +741,9 @@ def main():
                     help="only the circuit-family table (fusion none / size-only / adaptive, per pass and "
                          "cache-blocked); prints one JSON object")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the single-pass sweep (k = 1..6 x six gate kinds x three placements, 28 and 30 "
+                         "qubits, both dtypes); prints one JSON object")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="only the oracle's CPU baseline (no GPU); prints one JSON object")
     ap.add_argument("--cpu-target-s", type=float, default=15.0)
@@ -702,6 +781,9 @@ def main():
         return
     if args.jit:
         print(json.dumps(run_jit()), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps({"sweep": run_sweep()}), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -756,7 +838,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"qft{args.n}_complex128_kmax{args.k_max}", "n_qubits": args.n,
-                   "k_max": args.k_max, "fused_passes": main_run["passes"],
+                   "k_max": args.k_max, "fused_gates": main_run["fused_gates"], "passes": main_run["passes"],
                    "state_bytes": (1 << args.n) * 16},
         "roofline": roof,
         "c64_error_vs_fp64": c64_err,

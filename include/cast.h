@@ -156,15 +156,38 @@ cast_status fused_info(const cast_fused *f, size_t *n_fused, double *total_opcou
 cast_status fused_gate(const cast_fused *f, size_t i, int *k, int *qubits, double *opcount,
                        int *subspace_dim, int *active_blocks, double *matrix);
 
-/* Applies every fused gate, in order, to the state (one device pass each).
- * The state's n must equal the n given to fuse_circuit.  Queued on the
- * state's stream. */
+/* Applies every fused gate, in order, to the state: one device pass per
+ * fused gate, except that a run of consecutive diagonal fused gates is applied
+ * in one elementwise pass.  A product of diagonal gates is diagonal and costs
+ * one complex multiply per amplitude whatever its size (its operation count,
+ * Sec. III-C, does not grow), so the host multiplies the run, in FP64, into
+ * at most "diag_run_tables" phase tables of at most "diag_run_qubits" qubits
+ * each, and the pass multiplies each amplitude by the product of its entries
+ * (knob diag_run_tables = 0: one pass per fused gate).  The schedule is built
+ * for the state's dtype with the knobs current at first use and cached in the
+ * list (rebuilt when those knobs change).  The state's n must equal the n
+ * given to fuse_circuit.  Queued on the state's stream. */
 cast_status apply_circuit(cast_sv *sv, const cast_fused *f);
 
 /* Same as apply_circuit, but records a HIP event pair around every pass on
- * the state's stream and returns each pass's device time in pass_ms (n_fused
- * floats, milliseconds).  Synchronous.  For measurement. */
+ * the state's stream and returns each pass's device time in pass_ms (one
+ * float per pass of circuit_passes, milliseconds).  Synchronous.  For
+ * measurement. */
 cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *f, float *pass_ms);
+
+/* Number of device passes apply_circuit makes for a 2^n state of dtype dt
+ * with the current knobs (host only; builds and caches the schedule). */
+cast_status circuit_passes(const cast_fused *f, int n, cast_dtype dt, size_t *n_passes);
+
+/* Pass i of that schedule: the fused gates [first, first + count) it applies,
+ * its kernel (as fused_pass_info, plus 6 = diagonal run and -1 = identity),
+ * the number of phase tables of a diagonal run (0 otherwise), and its
+ * algorithmic HBM bytes and flops: for a diagonal run, every amplitude at
+ * which some phase table differs from 1 read and written once and one
+ * complex multiply (8 flops) each.  Any output may be NULL.  CAST_EINVAL for i out of
+ * range. */
+cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
+                              int *kernel, int *tables, double *alg_bytes, double *flops);
 
 /* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct
  * gather), 1 (LDS tile), 2 (LDS tile, two buffers), 3 (elementwise diagonal)
@@ -259,6 +282,9 @@ void fused_destroy(cast_fused *f);
  * "mfma_low_tile" (1: a matrix-core pass with d <= 4 and a target below bit 4
  * runs on the LDS tile when at most one target lies above the tile's
  * contiguous window or the gate has several blocks; 0: the direct gather),
+ * "diag_run_tables" (tables per diagonal-run pass, 0..4; 0 = no runs),
+ * "diag_run_qubits" (qubits per diagonal-run table, 4..8), "diag_run_unroll"
+ * (its chunks per thread: 1, 2, 4), "diag_run_grid" (its workgroup cap),
  * "persistent_spin_limit" (polls a persistent batch item makes before its
  * dependency wait gives up and the run fails with CAST_EHIP; read by
  * batch_create; 0 makes every item that has a dependency fail at once, which
@@ -276,6 +302,37 @@ cast_status tuning_get(const char *key, cast_dtype dt, int *value);
  * measurements. */
 cast_status cost_table_set(cast_dtype dt, int k, int d, double ms_per_gamp);
 cast_status cost_table_get(cast_dtype dt, int k, int d, double *ms_per_gamp);
+
+/* ------------------------------------------------------------ path planner */
+
+/* Measured rates the planner prices passes with, per dtype (Sec. III-C's
+ * idea of a cost model measured on the target, applied to whole plans).
+ * Keys: "bw0".."bw6" (GB/s of algorithmic bytes of a pass whose schedule
+ * kernel kind, as circuit_pass_info reports it, is 0..6), "fl4".."fl6"
+ * (GFLOP/s of the matrix-core passes by block dimension), "fl_vec" (GFLOP/s
+ * of the other kernels), "launch_ms" (fixed cost of one pass), "seg_bw"
+ * (GB/s of a cache-blocked segment's read and write of the state),
+ * "seg_gate0".."seg_gate3" (ms per 2^30 amplitudes per fused gate applied
+ * inside a segment, by block dimension; 0 = diagonal).  Values must be
+ * positive and finite.  Not thread-safe against concurrent planning. */
+cast_status path_cost_set(const char *key, cast_dtype dt, double value);
+cast_status path_cost_get(const char *key, cast_dtype dt, double *value);
+
+/* Predicted device time (ms) of applying f to a 2^n state of dtype dt with
+ * apply_circuit (path 0: a launch plus max(algorithmic bytes / rate, flops /
+ * rate) per pass) or apply_circuit_blocked (path 1: ordinary passes the same
+ * way, a segment one read and write of the state plus its gates' in-tile
+ * costs).  Host only. */
+cast_status predict_ms(const cast_fused *f, int n, cast_dtype dt, int path, double *ms);
+
+/* Fuses the circuit (fixed gates, as fuse_circuit) at every size limit
+ * k_lo..k_hi, the other fusion options from opts (NULL: defaults), prices
+ * each fused list on both paths with predict_ms, and returns the cheapest
+ * pair: *out (caller owns; fused_destroy), *path (0: apply_circuit, 1:
+ * apply_circuit_blocked), *k_max and, if not NULL, *predicted (ms).  Ties go
+ * to the smaller k_max and to path 0.  Host only. */
+cast_status plan_circuit(int n, const cast_gate *gates, size_t n_gates, cast_dtype dt, const cast_fusion_opts *opts,
+                         int k_lo, int k_hi, cast_fused **out, int *path, int *k_max, double *predicted);
 
 /* ------------------------------------------------------------ observables */
 

@@ -69,6 +69,10 @@ SIGNATURES = {
     "apply_circuit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fused_destroy": (None, [ctypes.c_void_p]),
     "apply_circuit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "circuit_passes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "circuit_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t), _c_int_p,
+                                         _c_int_p, _c_double_p, _c_double_p]),
     "fused_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _c_int_p,
                                        _c_int_p, _c_double_p, _c_double_p]),
     "apply_circuit_blocked": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -97,6 +101,12 @@ SIGNATURES = {
     "batch_destroy": (None, [ctypes.c_void_p]),
     "tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]),
     "tuning_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _c_int_p]),
+    "path_cost_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_double]),
+    "path_cost_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _c_double_p]),
+    "predict_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p]),
+    "plan_circuit": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(cast_gate), ctypes.c_size_t, ctypes.c_int,
+                                    ctypes.POINTER(cast_fusion_opts), ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_void_p), _c_int_p, _c_int_p, _c_double_p]),
     "cost_table_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
     "cost_table_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p]),
     "adjoint_grad_batch": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.c_int,
@@ -224,7 +234,10 @@ def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, aggl
 # --------------------------------------------------------------------- tuning
 TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "direct_chunk_log", "max_grid", "use_diag", "mfma_min_d",
                "mfma_grid_per_cu", "mfma_direct_min_q", "diag_unroll", "diag_max_grid", "diag_lds_table",
-               "diag_order", "blocked_tile_bits", "blocked_threads", "mfma_3m_min_d", "mfma_low_tile")
+               "diag_order", "blocked_tile_bits", "blocked_threads", "mfma_3m_min_d", "mfma_low_tile",
+               "persistent_spin_limit", "diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid")
+PATH_COST_KEYS = tuple(f"bw{i}" for i in range(7)) + ("fl4", "fl5", "fl6", "fl_vec", "launch_ms", "seg_bw") + \
+    tuple(f"seg_gate{d}" for d in range(4))
 #: environment overrides (set for sweeps) take precedence over the tuning file
 _ENV_OF = {"direct_min_q": "CAST_DIRECT_MIN_Q", "tile_bits": "CAST_TILE_BITS", "direct_ipt": "CAST_DIRECT_IPT",
            "direct_nt": "CAST_DIRECT_NT", "direct_chunk_log": "CAST_DIRECT_CHUNK_LOG", "max_grid": "CAST_MAX_GRID", "use_diag": "CAST_USE_DIAG",
@@ -262,11 +275,51 @@ def apply_tuning_file(path=TUNING_FILE):
             tuning_set(key.encode(), dt, int(value))
         for entry in data.get("cost", {}).get(dname, []):
             cost_table_set(dt, int(entry["k"]), int(entry["d"]), float(entry["ms_per_gamp"]))
+        for key, value in data.get("path_cost", {}).get(dname, {}).items():
+            path_cost_set(key.encode(), dt, float(value))
     return True
+
+
+def get_path_cost(key, dtype=torch.complex128):
+    v = ctypes.c_double()
+    path_cost_get(key.encode(), C128 if dtype == torch.complex128 else C64, ctypes.byref(v))
+    return v.value
+
+
+def set_path_cost(key, value, dtype=torch.complex128):
+    path_cost_set(key.encode(), C128 if dtype == torch.complex128 else C64, float(value))
+
+
+def plan(n, gates, dtype=torch.complex128, k_range=(2, 6), **opts):
+    """Fuses `gates` at every k_max in k_range and returns the cheapest
+    (fused list, path) under the measured path costs:
+    (FusedCircuit, path 0 per pass / 1 cache-blocked, k_max, predicted ms)."""
+    ga = GateArray(gates)
+    o = fusion_options(**opts)
+    h = ctypes.c_void_p()
+    path, kmax, pred = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    plan_circuit(n, ga.arr, ga.n, C128 if dtype == torch.complex128 else C64, ctypes.byref(o), int(k_range[0]),
+                 int(k_range[1]), ctypes.byref(h), ctypes.byref(path), ctypes.byref(kmax), ctypes.byref(pred))
+    return FusedCircuit._adopt(n, h), path.value, kmax.value, pred.value
 
 
 class FusedCircuit:
     """A fused gate list owned by the library."""
+
+    @classmethod
+    def _adopt(cls, n, handle):
+        """Wraps a fused list the library created (takes ownership)."""
+        self = cls.__new__(cls)
+        self.handle = handle
+        self.n = n
+        return self
+
+    def predict_ms(self, dtype, path):
+        """Predicted device time of apply_circuit (path 0) or
+        apply_circuit_blocked (path 1) under the measured path costs."""
+        v = ctypes.c_double()
+        predict_ms(self.handle, self.n, C128 if dtype == torch.complex128 else C64, int(path), ctypes.byref(v))
+        return v.value
 
     def __init__(self, n, gates, **opts):
         ga = GateArray(gates)
@@ -303,6 +356,28 @@ class FusedCircuit:
         fused_pass_info(self.handle, i, self.n, dt, ctypes.byref(kern), ctypes.byref(d), ctypes.byref(b),
                         ctypes.byref(f))
         return {"kernel": kern.value, "d": d.value, "alg_bytes": b.value, "flops": f.value}
+
+    def num_passes(self, dtype):
+        """Device passes apply_circuit makes for this dtype (current knobs)."""
+        dt = C128 if dtype == torch.complex128 else C64
+        npass = ctypes.c_size_t()
+        circuit_passes(self.handle, self.n, dt, ctypes.byref(npass))
+        return npass.value
+
+    def schedule(self, dtype):
+        """The passes of apply_circuit: fused gates covered, kernel, phase
+        tables of a diagonal run, algorithmic bytes and flops."""
+        dt = C128 if dtype == torch.complex128 else C64
+        out = []
+        for i in range(self.num_passes(dtype)):
+            first, count = ctypes.c_size_t(), ctypes.c_size_t()
+            kern, tabs = ctypes.c_int(), ctypes.c_int()
+            b, f = ctypes.c_double(), ctypes.c_double()
+            circuit_pass_info(self.handle, self.n, dt, i, ctypes.byref(first), ctypes.byref(count),
+                              ctypes.byref(kern), ctypes.byref(tabs), ctypes.byref(b), ctypes.byref(f))
+            out.append({"first": first.value, "count": count.value, "kernel": kern.value, "tables": tabs.value,
+                        "alg_bytes": b.value, "flops": f.value})
+        return out
 
     def blocked_passes(self, dtype):
         """The cache-blocked grouping on this circuit's n qubits in `dtype`:
@@ -367,8 +442,9 @@ class StateVector:
         apply_circuit(self.handle, fused.handle)
 
     def apply_circuit_timed(self, fused: FusedCircuit):
-        """Applies the circuit and returns per-pass device times (ms)."""
-        nf = len(fused)
+        """Applies the circuit and returns the device time (ms) of each pass
+        of its schedule (FusedCircuit.schedule)."""
+        nf = fused.num_passes(self.tensor.dtype)
         out = (ctypes.c_float * max(1, nf))()
         apply_circuit_timed(self.handle, fused.handle, out)
         return np.array(out[:nf], dtype=np.float64)

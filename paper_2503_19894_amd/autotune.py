@@ -124,10 +124,92 @@ def cost_table(n, dtype, log):
     return out
 
 
+def _timed_passes(sv, fc, reps=3):
+    """Best-of-reps device time of each pass of fc's schedule (ms)."""
+    sv.apply_circuit(fc)
+    return np.min([sv.apply_circuit_timed(fc) for _ in range(reps)], axis=0)
+
+
+def path_costs(n, dtype, log):
+    """Rates the path planner prices plans with (measured on 2^n states):
+    algorithmic GB/s of each pass kernel, the matrix cores' GFLOP/s by block
+    dimension, the fixed cost of a pass, and for cache-blocked segments the
+    state read/write rate and the in-tile cost per gate by block dimension
+    (a linear fit over segments of different lengths)."""
+    rng = np.random.default_rng(2)
+    psi = torch.zeros(1 << n, dtype=dtype, device="cuda")
+    psi[0] = 1
+    sv = cast.StateVector(n, tensor=psi)
+    rates = {}   # kind -> [GB/s]
+    fl = {}
+    cases = []
+    for k in (2, 3):
+        cases += [gate_sweep("haar", k, tuple(range(n - k, n)), seed=k), gate_sweep("haar", k, tuple(range(k)), seed=k),
+                  gate_sweep("diag", k, tuple(sorted(rng.permutation(n)[:k])), seed=k)]
+    for k in (4, 5, 6):
+        cases += [gate_sweep("haar", k, tuple(range(n - k, n)), seed=k), gate_sweep("haar", k, tuple(range(k)), seed=k)]
+    for gates in cases:
+        k = max(len(g.qubits) for g in gates)
+        fc = cast.FusedCircuit(n, gates, k_max=k)
+        inf = fc.schedule(dtype)[0]
+        t = float(_timed_passes(sv, fc)[0])
+        rates.setdefault(inf["kernel"], []).append(inf["alg_bytes"] / (t * 1e-3) / 1e9)
+        if inf["kernel"] in (4, 5):
+            d = fc.gate(0)["d"]
+            fl.setdefault(d, []).append(inf["flops"] / (t * 1e-3) / 1e9)
+    fc = cast.FusedCircuit(n, qft(n), k_max=5)
+    sched = fc.schedule(dtype)
+    ts = _timed_passes(sv, fc)
+    for inf, t in zip(sched, ts):
+        if inf["kernel"] >= 0 and inf["alg_bytes"] > 0:
+            rates.setdefault(inf["kernel"], []).append(inf["alg_bytes"] / (t * 1e-3) / 1e9)
+    out = {f"bw{kind}": float(np.median(v)) for kind, v in rates.items()}
+    out.update({f"fl{d}": float(np.median(v)) for d, v in fl.items()})
+    # fixed cost: passes on a small state
+    small = cast.StateVector(12, dtype=dtype)
+    fc = cast.FusedCircuit(12, gate_sweep("haar", 2, (10, 11), seed=1) * 1, k_max=2)
+    out["launch_ms"] = float(np.median(_timed_passes(small, fc, reps=7)))
+    # segments: m gates of block dimension d on the low qubits, one segment
+    seg = {}
+    for d in (0, 1, 2, 3):
+        pts = []
+        for m in (4, 24):
+            gates = []
+            for i in range(m):
+                qs = tuple(sorted(rng.permutation(8)[:max(d, 1) + (1 if d == 0 else 0)]))
+                if d == 0:
+                    gates.append(Gate("unitary", qs, matrix=np.diag(np.exp(1j * rng.uniform(0.1, 6, 1 << len(qs))))))
+                else:
+                    gates.append(Gate("unitary", qs, matrix=haar_unitary(1 << d, rng)))
+            fc = cast.FusedCircuit(n, gates, k_max=1)
+            bp = fc.blocked_passes(dtype)
+            if len(bp) != 1 or not bp[0]["tile_bits"]:
+                continue
+            sv.apply_circuit_blocked(fc)
+            t = min(float(sv.apply_circuit_blocked_timed(fc)[0]) for _ in range(3))
+            pts.append((len(fc), t))
+        if len(pts) == 2 and pts[1][0] > pts[0][0]:
+            (m0, t0), (m1, t1) = pts
+            b = (t1 - t0) / (m1 - m0)
+            seg[d] = (max(b, 1e-4) * 2.0 ** (30 - n), t0 - b * m0)
+    for d, (per_gate, _) in seg.items():
+        out[f"seg_gate{d}"] = per_gate
+    base = [a for _, a in seg.values() if a > 0]
+    if base:
+        S = (1 << n) * (16 if dtype == torch.complex128 else 8)
+        out["seg_bw"] = 2.0 * S / (max(float(np.median(base)) - out["launch_ms"], 1e-3) * 1e-3) / 1e9
+    del sv, psi, small
+    torch.cuda.empty_cache()
+    log("  " + ", ".join(f"{k}={v:.4g}" for k, v in sorted(out.items())))
+    return {k: v for k, v in out.items() if v > 0 and np.isfinite(v)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--out", default=os.path.join(HERE, "tuning_gfx950.json"))
+    ap.add_argument("--path-costs-only", action="store_true",
+                    help="keep the knobs and cost table of the existing file; measure only the path costs")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         sys.exit("autotune needs a GPU")
@@ -136,6 +218,17 @@ def main():
         print(msg, flush=True)
 
     t0 = time.time()
+    if args.path_costs_only:
+        result = json.load(open(args.out))
+        result["path_cost"] = {}
+        for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+            log(f"{dname}: path costs")
+            result["path_cost"][dname] = path_costs(args.n, dtype, log)
+        result["seconds_path_cost"] = round(time.time() - t0, 1)
+        with open(args.out, "w") as f:
+            json.dump(result, f, indent=1)
+        log(f"wrote {args.out}")
+        return
     result = {"device": torch.cuda.get_device_properties(0).gcnArchName, "n_qubits": args.n,
               "knobs": {}, "cost": {}}
     for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
@@ -143,6 +236,10 @@ def main():
         result["knobs"][dname] = tune_knobs(args.n, dtype, log)
         log(f"{dname}: cost table (ms per 2^30 amplitudes)")
         result["cost"][dname] = cost_table(args.n, dtype, log)
+        log(f"{dname}: path costs")
+        result.setdefault("path_cost", {})[dname] = path_costs(args.n, dtype, log)
+        for key, v in result["path_cost"][dname].items():
+            cast.set_path_cost(key, v, dtype)
     result["seconds"] = round(time.time() - t0, 1)
     with open(args.out, "w") as f:
         json.dump(result, f, indent=1)

@@ -429,6 +429,10 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "blocked_tile_bits") { *lo = 8; *hi = i == CAST_C64 ? 13 : 12; return &t.blocked_tile_bits[i]; }
     if (key == "blocked_threads") { *lo = 256; *hi = 1024; return &t.blocked_threads[i]; }
     if (key == "persistent_spin_limit") return &t.persistent_spin_limit[i];
+    if (key == "diag_run_tables") { *hi = kRunMaxTables; return &t.diag_run_tables[i]; }
+    if (key == "diag_run_qubits") { *lo = 4; *hi = kRunMaxQ; return &t.diag_run_qubits[i]; }
+    if (key == "diag_run_unroll") { *lo = 1; *hi = 4; return &t.diag_run_unroll[i]; }
+    if (key == "diag_run_grid") { *lo = 256; return &t.diag_run_grid[i]; }
     return nullptr;
 }
 
@@ -439,6 +443,7 @@ cast_status tuning_set(const char *key, cast_dtype dt, int value) {
     if (!f) return fail(CAST_EINVAL, std::string("unknown tuning key ") + key);
     if (value < lo || value > hi || (std::string(key) == "direct_ipt" && value == 3) ||
         (std::string(key) == "diag_unroll" && (value & (value - 1))) ||
+        (std::string(key) == "diag_run_unroll" && (value & (value - 1))) ||
         (std::string(key) == "blocked_threads" && (value & (value - 1))))
         return fail(CAST_EINVAL, std::string("value out of range for ") + key);
     *f = value;
@@ -560,41 +565,77 @@ cast_status fused_gate(const cast_fused *f, size_t i, int *k, int *qubits, doubl
     return CAST_OK;
 }
 
-cast_status apply_circuit(cast_sv *sv, const cast_fused *fc) {
+}  // extern "C"
+
+namespace cast {
+
+// The pass schedule of a fused list for (n, dt), built with the current knobs
+// and cached in the list; with `upload`, its run tables are on the device.
+static cast_status get_schedule(cast_fused *f, int n, cast_dtype dt, bool upload, Schedule **out) {
+    const Tuning &tu = tuning();
+    Schedule *s = f->sched[dt];
+    if (s && (s->n != n || s->run_tables != tu.diag_run_tables[dt] || s->run_qubits != tu.diag_run_qubits[dt] ||
+              s->use_diag != tu.use_diag[dt])) {
+        schedule_free(s);
+        s = f->sched[dt] = nullptr;
+    }
+    if (!s) {
+        s = new Schedule;
+        if (cast_status rc = build_schedule(f->plans, n, dt, s)) {
+            delete s;
+            return rc;
+        }
+        f->sched[dt] = s;
+    }
+    if (upload && !s->dev.ptr)
+        if (cast_status rc = upload_schedule(s)) return rc;
+    *out = s;
+    return CAST_OK;
+}
+
+static cast_status launch_sched_pass(cast_sv *sv, cast_fused *f, const Schedule &sc, const SchedPass &sp) {
+    if (sp.kind == 6) return launch_diag_run(sv->data, sv->n, sv->dt, sp, sc.dev.ptr, sv->stream);
+    const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
+    const void *dm = (const char *)f->dev[sv->dt].ptr + f->dev_off[sv->dt][sp.first] * rsz;
+    return launch_pass(sv->data, sv->n, sv->dt, f->plans[sp.first], dm, sv->stream);
+}
+
+static cast_status prepare_circuit(cast_sv *sv, const cast_fused *fc, cast_fused **f, Schedule **sc) {
     if (cast_status rc = check_sv(sv)) return rc;
     if (!fc) return fail(CAST_EINVAL, "fused list is NULL");
     if (fc->n != sv->n) return fail(CAST_EINVAL, "fused list was built for a different qubit count");
-    cast_fused *f = const_cast<cast_fused *>(fc);
+    *f = const_cast<cast_fused *>(fc);
     const int dt = sv->dt;
-    if (!f->dev[dt].ptr && !f->plans.empty()) {
-        if (cast_status rc = upload_plans(f->plans, sv->dt, &f->dev[dt], &f->dev_off[dt])) return rc;
-    }
-    const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
-    for (size_t i = 0; i < f->plans.size(); ++i) {
-        const void *dm = (const char *)f->dev[dt].ptr + f->dev_off[dt][i] * rsz;
-        if (cast_status rc = launch_pass(sv->data, sv->n, sv->dt, f->plans[i], dm, sv->stream)) return rc;
-    }
+    if (!(*f)->dev[dt].ptr && !(*f)->plans.empty())
+        if (cast_status rc = upload_plans((*f)->plans, sv->dt, &(*f)->dev[dt], &(*f)->dev_off[dt])) return rc;
+    return get_schedule(*f, sv->n, sv->dt, true, sc);
+}
+
+}  // namespace cast
+
+extern "C" {
+
+cast_status apply_circuit(cast_sv *sv, const cast_fused *fc) {
+    cast_fused *f;
+    Schedule *sc;
+    if (cast_status rc = prepare_circuit(sv, fc, &f, &sc)) return rc;
+    for (const SchedPass &sp : sc->passes)
+        if (cast_status rc = launch_sched_pass(sv, f, *sc, sp)) return rc;
     return CAST_OK;
 }
 
 cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *fc, float *pass_ms) {
-    if (cast_status rc = check_sv(sv)) return rc;
-    if (!fc || !pass_ms) return fail(CAST_EINVAL, "NULL argument");
-    if (fc->n != sv->n) return fail(CAST_EINVAL, "fused list was built for a different qubit count");
-    cast_fused *f = const_cast<cast_fused *>(fc);
-    const int dt = sv->dt;
-    if (!f->dev[dt].ptr && !f->plans.empty()) {
-        if (cast_status rc = upload_plans(f->plans, sv->dt, &f->dev[dt], &f->dev_off[dt])) return rc;
-    }
-    const size_t np = f->plans.size();
+    if (!pass_ms) return fail(CAST_EINVAL, "NULL argument");
+    cast_fused *f;
+    Schedule *sc;
+    if (cast_status rc = prepare_circuit(sv, fc, &f, &sc)) return rc;
+    const size_t np = sc->passes.size();
     std::vector<hipEvent_t> ev(np + 1);
     for (auto &e : ev) CAST_HIP_TRY(hipEventCreate(&e));
-    const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
     cast_status rc = CAST_OK;
     CAST_HIP_TRY(hipEventRecord(ev[0], sv->stream));
     for (size_t i = 0; i < np && !rc; ++i) {
-        const void *dm = (const char *)f->dev[dt].ptr + f->dev_off[dt][i] * rsz;
-        rc = launch_pass(sv->data, sv->n, sv->dt, f->plans[i], dm, sv->stream);
+        rc = launch_sched_pass(sv, f, *sc, sc->passes[i]);
         if (!rc) CAST_HIP_TRY(hipEventRecord(ev[i + 1], sv->stream));
     }
     if (!rc) {
@@ -603,6 +644,37 @@ cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *fc, float *pass_m
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return rc;
+}
+
+cast_status circuit_passes(const cast_fused *fc, int n, cast_dtype dt, size_t *n_passes) {
+    if (!fc || !n_passes) return fail(CAST_EINVAL, "NULL argument");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n != fc->n) return fail(CAST_EINVAL, "n differs from the fused list's");
+    Schedule *sc;
+    if (cast_status rc = get_schedule(const_cast<cast_fused *>(fc), n, dt, false, &sc)) return rc;
+    *n_passes = sc->passes.size();
+    return CAST_OK;
+}
+
+cast_status circuit_pass_info(const cast_fused *fc, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
+                              int *kernel, int *tables, double *alg_bytes, double *flops) {
+    if (!fc) return fail(CAST_EINVAL, "fused list is NULL");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n != fc->n) return fail(CAST_EINVAL, "n differs from the fused list's");
+    Schedule *sc;
+    if (cast_status rc = get_schedule(const_cast<cast_fused *>(fc), n, dt, false, &sc)) return rc;
+    if (i >= sc->passes.size()) return fail(CAST_EINVAL, "pass index out of range");
+    const SchedPass &sp = sc->passes[i];
+    if (first) *first = sp.first;
+    if (count) *count = sp.count;
+    if (kernel) *kernel = sp.kind;
+    if (tables) *tables = (int)sp.tabs.size();
+    if (sp.kind == 6) {
+        if (alg_bytes) *alg_bytes = 2.0 * (double)amp_bytes(dt) * sp.active_amps;
+        if (flops) *flops = 8.0 * sp.active_amps;
+        return CAST_OK;
+    }
+    return fused_pass_info(fc, sp.first, n, dt, nullptr, nullptr, alg_bytes, flops);
 }
 
 cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt, int *kernel, int *d,
@@ -622,7 +694,8 @@ cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt,
 
 void fused_destroy(cast_fused *f) {
     if (!f) return;
-    for (int d = 0; d < 3; ++d) dev_free(f->dev[d].ptr), blocked_free(f->blocked[d]), jit_free(f->jit[d]);
+    for (int d = 0; d < 3; ++d)
+        dev_free(f->dev[d].ptr), blocked_free(f->blocked[d]), jit_free(f->jit[d]), schedule_free(f->sched[d]);
     delete f;
 }
 

@@ -86,6 +86,12 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     // persistent batch launch: polls before a dependency wait gives up; 0
     // makes every dependency fail at once (exercises the error path)
     int persistent_spin_limit[3] = {0, 1 << 24, 1 << 24};
+    // diagonal runs: tables per merged elementwise pass (0: one pass per
+    // fused gate), qubits per table, chunks per thread, workgroup cap
+    int diag_run_tables[3] = {0, 4, 3};
+    int diag_run_qubits[3] = {0, 8, 8};
+    int diag_run_unroll[3] = {0, 2, 2};
+    int diag_run_grid[3] = {0, 4096, 4096};
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).
@@ -126,6 +132,39 @@ cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceM
                          std::vector<size_t> *offsets);
 // The offsets (in reals) upload_plans gives each plan, computed on the host.
 std::vector<size_t> plan_offsets(const std::vector<PassPlan> &ps, cast_dtype dt);
+
+// ----------------------------------------------------------------- pass schedule
+// The passes apply_circuit makes: one per fused gate, except that a run of
+// consecutive diagonal fused gates is applied in one elementwise pass with
+// its phases combined into at most kRunMaxTables tables of at most kRunMaxQ
+// qubits (diagrun.hip).
+constexpr int kRunMaxTables = 4;
+constexpr int kRunMaxQ = 8;
+struct PhaseTable {                  // phases over k sorted qubits, entry j: bit i <-> q[i]
+    int k = 0;
+    int q[kRunMaxQ] = {0};
+    std::vector<cplx> ph;
+};
+struct SchedPass {
+    size_t first = 0, count = 1;     // fused gates [first, first + count)
+    int kind = 0;                    // pass_kernel_kind of a single gate, -1 identity, 6 diagonal run
+    std::vector<PhaseTable> tabs;    // kind 6
+    size_t tab_off = 0;              // kind 6: entry offset of its tables in the device buffer
+    double active_amps = 0;          // kind 6: amplitudes at which some table differs from 1
+};
+struct Schedule {
+    int n = 0;
+    cast_dtype dt = CAST_C128;
+    int run_tables = 0, run_qubits = 0, use_diag = 0;   // knobs it was built with
+    std::vector<SchedPass> passes;
+    DeviceMatrix dev;                // run tables in the state dtype, 256 entries per table
+};
+bool diag_pass(int n, cast_dtype dt, const PassPlan &p);
+cast_status build_schedule(const std::vector<PassPlan> &plans, int n, cast_dtype dt, Schedule *out);
+cast_status upload_schedule(Schedule *s);
+cast_status launch_diag_run(void *psi, int n, cast_dtype dt, const SchedPass &p, const void *dtabs,
+                            hipStream_t stream);
+void schedule_free(Schedule *s);
 
 // Device allocation with the CAST_MAX_DEVICE_BYTES cap.
 cast_status dev_alloc(void **ptr, size_t bytes);
@@ -173,4 +212,6 @@ struct cast_fused {
     cast::BlockedPlan *blocked[3] = {nullptr, nullptr, nullptr};
     // generated kernels, per dtype (compiled on first use)
     cast::JitModule *jit[3] = {nullptr, nullptr, nullptr};
+    // pass schedule of apply_circuit, per dtype (built on first use)
+    cast::Schedule *sched[3] = {nullptr, nullptr, nullptr};
 };

@@ -189,6 +189,30 @@ int main() {
             fused_destroy(f);
         }
     }
+    // path planner: pricing and plan choice over k_max 1..6
+    {
+        auto circ = random_circuit(16, 80, rng);
+        auto gv = view(circ);
+        for (cast_dtype dt : {CAST_C64, CAST_C128}) {
+            cast_fused *f = nullptr;
+            int path = -1, k = -1;
+            double ms = 0;
+            EXPECT(plan_circuit(16, gv.data(), gv.size(), dt, nullptr, 1, 6, &f, &path, &k, &ms) == CAST_OK);
+            EXPECT(f != nullptr && (path == 0 || path == 1) && k >= 1 && k <= 6 && ms > 0);
+            double p0 = 0, p1 = 0;
+            EXPECT(predict_ms(f, 16, dt, 0, &p0) == CAST_OK);
+            EXPECT(predict_ms(f, 16, dt, 1, &p1) == CAST_OK);
+            EXPECT(predict_ms(f, 16, dt, 2, &p1) == CAST_EINVAL);
+            fused_destroy(f);
+            double v = 0;
+            EXPECT(path_cost_get("seg_gate2", dt, &v) == CAST_OK && v > 0);
+            EXPECT(path_cost_set("seg_gate2", dt, v) == CAST_OK);
+            EXPECT(path_cost_set("bw7", dt, 1.0) == CAST_EINVAL);
+        }
+        cast_fused *f = nullptr;
+        int path, k;
+        EXPECT(plan_circuit(16, gv.data(), gv.size(), CAST_C128, nullptr, 3, 2, &f, &path, &k, nullptr) == CAST_EINVAL);
+    }
     // validation paths
     {
         fusion_opts_default(&o);
