@@ -88,32 +88,52 @@ class Tile {
 
     void init_last() { last_.assign(n_, -1); }
 
+    // One traversal of the tile (Sec. III-B, Alg. 1): rows top to bottom;
+    // in each row every occupied cell first lets its block settle (sink into
+    // free space or take in the block under that cell), then blocks standing
+    // side by side in the row are merged.  Returns whether anything fused.
     bool traverse(int k) {
-        bool delta = false;
+        bool fused = false;
         for (size_t r = 0; r < rows_.size(); ++r) {
-            for (int q = 0; q < n_; ++q) {
-                const int bt = rows_[r][q];
-                if (bt < 0) continue;
-                if (r + 1 >= rows_.size()) continue;
-                if (cells_free(r + 1, blocks_[bt].qubits, -1)) {
-                    move(bt, r, r + 1);  // move down; it is handled again at row r + 1
-                    continue;
-                }
-                const int bb = rows_[r + 1][q];
-                if (bb >= 0 && bb != bt && fusible(bt, bb, k)) {
-                    fuse_consecutive(bt, bb, r);
-                    delta = true;
-                }
-            }
-            for (int q = 1; q < n_; ++q) {
-                const int a = rows_[r][q - 1], b = rows_[r][q];
-                if (a >= 0 && b >= 0 && a != b && fusible(a, b, k)) {
-                    place(fuse_pair(a, b), r, r);
-                    delta = true;
-                }
-            }
+            // rows are only ever inserted below r, so a last row stays last
+            if (r + 1 < rows_.size())
+                for (int q = 0; q < n_; ++q) fused |= settle_cell(r, q, k);
+            fused |= merge_neighbours(r, k);
         }
-        return delta;
+        return fused;
+    }
+
+    // The block at cell (r, q), if any, sinks one row when every cell it needs
+    // in row r + 1 is empty -- a move, not a fusion: it meets the block below
+    // when the walk reaches row r + 1 -- and otherwise absorbs the block right
+    // under this cell when the pair is fusible (consecutive fusion).  A
+    // multi-qubit block is settled once per cell, so it can absorb a block
+    // under any of its qubits.
+    bool settle_cell(size_t r, int q, int k) {
+        const int upper = rows_[r][q];
+        if (upper < 0) return false;
+        if (cells_free(r + 1, blocks_[upper].qubits, -1)) {
+            move(upper, r, r + 1);
+            return false;
+        }
+        const int lower = rows_[r + 1][q];
+        if (lower < 0 || lower == upper || !fusible(upper, lower, k)) return false;
+        fuse_consecutive(upper, lower, r);
+        return true;
+    }
+
+    // Neighbouring cells (q - 1, q) of row r holding different blocks: the
+    // two act at the same step on disjoint qubits, so they commute, and they
+    // are fused when fusible (commuting fusion).
+    bool merge_neighbours(size_t r, int k) {
+        bool fused = false;
+        for (int q = 1; q < n_; ++q) {
+            const int a = rows_[r][q - 1], b = rows_[r][q];
+            if (a < 0 || b < 0 || a == b || !fusible(a, b, k)) continue;
+            place(fuse_pair(a, b), r, r);
+            fused = true;
+        }
+        return fused;
     }
 
     // Re-appends every block in time order: removes empty rows and lifts
