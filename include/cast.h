@@ -57,6 +57,14 @@ typedef struct cast_fused cast_fused; /* opaque fused-gate list, ready to apply 
 /* Thread-local message of the last failing call ("" if none). */
 const char *cast_last_error(void);
 
+/* expval and adjoint_grad take their device scratch (reduction partials,
+ * work states, matrices) from a reuse pool instead of allocating and freeing
+ * it on every call; a block returns to the pool once its call has finished
+ * its device work, and at most 8 GiB stay pooled (counted against
+ * CAST_MAX_DEVICE_BYTES).  pool_trim frees everything pooled.  Not to be
+ * called while those calls run on other threads. */
+void pool_trim(void);
+
 /* ------------------------------------------------------------------ states */
 
 /* Allocates a 2^n state of dtype `dt` (1 <= n <= 34) on the current HIP

@@ -50,6 +50,7 @@ class cast_pauli_term(ctypes.Structure):
 #: exported symbol -> (restype, argtypes); the same list tests check against include/cast.h
 SIGNATURES = {
     "cast_last_error": (ctypes.c_char_p, []),
+    "pool_trim": (None, []),
     "sv_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "sv_wrap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                ctypes.POINTER(ctypes.c_void_p)]),

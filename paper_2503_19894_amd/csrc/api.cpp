@@ -113,6 +113,61 @@ cast_status dev_alloc(void **ptr, size_t bytes) {
     return CAST_OK;
 }
 
+// Reuse pool for per-call scratch (expval, adjoint_grad): blocks are kept
+// per device in power-of-two size classes and handed out again instead of
+// being freed, so a call makes no hipMalloc/hipFree (each free synchronises
+// the device) once the pool holds its sizes.  A block goes back only after
+// its call has synchronised its stream.  At most kPoolKeep bytes stay pooled.
+namespace {
+struct PoolBlock {
+    void *p;
+    size_t bytes;
+    int dev;
+};
+std::mutex g_pool_mu;
+std::vector<PoolBlock> g_pool;
+size_t g_pool_bytes = 0;
+constexpr size_t kPoolKeep = size_t(8) << 30;
+size_t pool_class(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+}  // namespace
+
+cast_status pool_alloc(void **ptr, size_t bytes, size_t *cls) {
+    *cls = pool_class(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (size_t i = 0; i < g_pool.size(); ++i)
+            if (g_pool[i].bytes == *cls && g_pool[i].dev == dev) {
+                *ptr = g_pool[i].p;
+                g_pool_bytes -= g_pool[i].bytes;
+                g_pool[i] = g_pool.back();
+                g_pool.pop_back();
+                return CAST_OK;
+            }
+    }
+    return dev_alloc(ptr, *cls);
+}
+
+void pool_free(void *ptr, size_t cls) {
+    if (!ptr) return;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (g_pool_bytes + cls <= kPoolKeep) {
+            g_pool.push_back(PoolBlock{ptr, cls, dev});
+            g_pool_bytes += cls;
+            return;
+        }
+    }
+    dev_free(ptr);
+}
+
 void dev_free(void *ptr) {
     if (!ptr) return;
     size_t bytes = 0;
@@ -162,6 +217,25 @@ std::vector<size_t> plan_offsets(const std::vector<PassPlan> &ps, cast_dtype dt)
     std::vector<size_t> off;
     pack_all(ps, dt, hd, hf, &off);
     return off;
+}
+
+cast_status upload_plans_pooled(const std::vector<PassPlan> &ps, cast_dtype dt, void **ptr, size_t *cls,
+                                std::vector<size_t> *offsets) {
+    std::vector<double> hd;
+    std::vector<float> hf;
+    const size_t elems = pack_all(ps, dt, hd, hf, offsets);
+    const size_t bytes = elems * (dt == CAST_C128 ? 8 : 4);
+    if (cast_status st = pool_alloc(ptr, bytes, cls)) return st;
+    if (bytes) {
+        const hipError_t e = hipMemcpy(*ptr, dt == CAST_C128 ? (void *)hd.data() : (void *)hf.data(), bytes,
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            pool_free(*ptr, *cls);
+            *ptr = nullptr;
+            return fail(CAST_EHIP, std::string("matrix upload: ") + hipGetErrorString(e));
+        }
+    }
+    return CAST_OK;
 }
 
 cast_status upload_plans(const std::vector<PassPlan> &ps, cast_dtype dt, DeviceMatrix *out,
@@ -281,6 +355,22 @@ using namespace cast;
 extern "C" {
 
 const char *cast_last_error(void) { return g_err.c_str(); }
+
+void pool_trim(void) {
+    std::vector<PoolBlock> blocks;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        blocks.swap(g_pool);
+        g_pool_bytes = 0;
+    }
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (const PoolBlock &b : blocks) {
+        (void)hipSetDevice(b.dev);
+        dev_free(b.p);
+    }
+    (void)hipSetDevice(cur);
+}
 
 // ----------------------------------------------------------------- states
 cast_status sv_create(int n, cast_dtype dt, void *hip_stream, cast_sv **out) {

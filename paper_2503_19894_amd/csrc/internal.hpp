@@ -169,6 +169,13 @@ void schedule_free(Schedule *s);
 // Device allocation with the CAST_MAX_DEVICE_BYTES cap.
 cast_status dev_alloc(void **ptr, size_t bytes);
 void dev_free(void *ptr);
+// Pooled scratch: *cls receives the block's size class, which pool_free
+// needs back.  Return a block only once the work using it has completed.
+cast_status pool_alloc(void **ptr, size_t bytes, size_t *cls);
+void pool_free(void *ptr, size_t cls);
+// upload_plans into a pooled block (synchronous copy).
+cast_status upload_plans_pooled(const std::vector<PassPlan> &ps, cast_dtype dt, void **ptr, size_t *cls,
+                                std::vector<size_t> *offsets);
 
 // ----------------------------------------------------------------- fusion
 struct FusionGate {                  // a gate as fusion sees it

@@ -45,11 +45,20 @@ static cast_status check_terms(int n, const cast_pauli_term *t, size_t nt) {
     return CAST_OK;
 }
 
-// RAII device buffer
+// RAII device scratch from the reuse pool.  The block goes back only after
+// its stream has drained (a no-op when the call already synchronised), so
+// an early error return never hands out memory that queued work still uses.
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf() { dev_free(p); }
-    cast_status alloc(size_t bytes) { return dev_alloc(&p, bytes); }
+    size_t cls = 0;
+    hipStream_t s = nullptr;
+    explicit DevBuf(hipStream_t stream) : s(stream) {}
+    ~DevBuf() {
+        if (!p) return;
+        (void)hipStreamSynchronize(s);
+        pool_free(p, cls);
+    }
+    cast_status alloc(size_t bytes) { return pool_alloc(&p, bytes, &cls); }
     template <typename T> T *as() const { return (T *)p; }
 };
 
@@ -88,7 +97,7 @@ cast_status expval(const cast_sv *sv, const cast_pauli_term *terms, size_t n_ter
     out[0] = out[1] = 0.0;
     if (!n_terms) return CAST_OK;
     Grouped g = group_by_x(terms, n_terms);
-    DevBuf scratch, res;
+    DevBuf scratch(sv->stream), res(sv->stream);
     if (cast_status rc = scratch.alloc(reduce_scratch_doubles() * sizeof(double))) return rc;
     if (cast_status rc = res.alloc(2 * n_terms * sizeof(double))) return rc;
     std::vector<size_t> slot_of(n_terms);
@@ -165,16 +174,14 @@ cast_status adjoint_grad(const cast_sv *init, const cast_gate *gates, size_t n_g
         plans.push_back(std::move(pf));
         plans.push_back(std::move(pb));
     }
-    DeviceMatrix dm;
     std::vector<size_t> off;
-    if (cast_status rc = upload_plans(plans, dt, &dm, &off)) return rc;
-    DevBuf mats;
-    mats.p = dm.ptr;
+    DevBuf mats(s);
+    if (cast_status rc = upload_plans_pooled(plans, dt, &mats.p, &mats.cls, &off)) return rc;
     const size_t rsz = dt == CAST_C128 ? 8 : 4;
-    auto mat_of = [&](size_t i) { return (const void *)((const char *)dm.ptr + off[i] * rsz); };
+    auto mat_of = [&](size_t i) { return (const void *)((const char *)mats.p + off[i] * rsz); };
 
     const size_t sbytes = ((size_t)1 << n) * amp_bytes(dt);
-    DevBuf psi, lam, scratch, res, tgroups, tterms;
+    DevBuf psi(s), lam(s), scratch(s), res(s), tgroups(s), tterms(s);
     if (cast_status rc = psi.alloc(sbytes)) return rc;
     if (cast_status rc = lam.alloc(sbytes)) return rc;
     if (cast_status rc = scratch.alloc(reduce_scratch_doubles() * sizeof(double))) return rc;

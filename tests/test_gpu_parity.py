@@ -350,3 +350,31 @@ def test_device_byte_cap_accounting():
     print(r.stdout, r.stderr[-2000:], flush=True)
     assert r.returncode == 0
     assert "second -2" in r.stdout and "third ok" in r.stdout
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_pooled_scratch_reuse(dtype):
+    """adjoint_grad and expval take their scratch from the reuse pool: calls
+    that reuse pooled blocks (and calls after pool_trim) give bit-identical
+    results, on different state sizes in turn."""
+    outs = {}
+    for rep in range(3):
+        for n in (7, 10):
+            gates, P = hea_vqa(n, 2)
+            H = vqa_hamiltonian(n)
+            th = vqa_thetas(P, 1, seed=n)[0]
+            init = cast.StateVector(n, dtype=dtype)
+            e, g = cast.adjoint(init, gates, th, H)
+            ev = init.expval(H)
+            key = (n,)
+            if key in outs:
+                assert outs[key][0] == e and np.array_equal(outs[key][1], g) and outs[key][2] == ev
+            else:
+                outs[key] = (e, g.copy(), ev)
+        if rep == 1:
+            cast.pool_trim()
+    for n in (7, 10):
+        gates, P = hea_vqa(n, 2)
+        ew, gw = oracle.adjoint_grad(n, gates, vqa_thetas(P, 1, seed=n)[0], vqa_hamiltonian(n))
+        tol = 1e-10 if dtype == torch.complex128 else 5e-4
+        assert abs(outs[(n,)][0] - ew) <= tol and np.max(np.abs(outs[(n,)][1] - gw)) <= tol
