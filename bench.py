@@ -201,7 +201,8 @@ def run_families(n=30, dtype_names=("c128", "c64")):
     (none = k_max 1, size-only k_max 5, adaptive k_max 5 with the measured
     cost table, and size-only k_max 2, 3, 4) the fused-gate count, host fusion
     time, one-pass-per-gate time and cache-blocked time (one warm-up
-    application each, then one timed)."""
+    application each, then one timed); then the path planner's choice of
+    k_max in 2..6 and execution path, with its predicted and measured time."""
     import torch
 
     import paper_2503_19894_amd as cast
@@ -234,6 +235,22 @@ def run_families(n=30, dtype_names=("c128", "c64")):
                 row["hbm_passes_blocked"] = len(fc.blocked_passes(dtype))
                 res[fam][mode] = row
                 del fc
+            # the path planner: fusion size and execution path chosen from the
+            # measured path costs, then timed on the path it chose
+            print(f"[bench] families {dname} {fam} planned", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            fc, path, k, pred = cast.plan(n, gates, dtype, k_range=(2, 6))
+            plan_ms = (time.perf_counter() - t0) * 1e3
+            apply = sv.apply_circuit_blocked if path == 1 else sv.apply_circuit
+            apply(fc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            apply(fc)
+            torch.cuda.synchronize()
+            res[fam]["planned"] = {"k_max": k, "path": "blocked" if path == 1 else "per_pass", "fused": len(fc),
+                                   "predicted_s": round(pred / 1e3, 4), "s": round(time.perf_counter() - t0, 4),
+                                   "planning_ms": round(plan_ms, 1)}
+            del fc
         out[dname] = res
         del sv, psi
         torch.cuda.empty_cache()
@@ -631,26 +648,53 @@ def host_description():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_total_gib": round(mem / 2**20, 1)}
 
 
-TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "k_diag_qft30_c128_hbm_traffic.txt")
-KERNEL_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19894_amd", "csrc",
-                             "apply.hip")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_19894_amd", "csrc")
+# kernel name prefix -> the source file that defines it
+KERNEL_FILES = (("k_diag_run", "diagrun.hip"), ("k_blocked", "blocked.hip"), ("k_batch", "batch_kernels.hip"),
+                ("k_pauli", "reduce.hip"), ("k_apply_pauli", "reduce.hip"), ("k_finish", "reduce.hip"),
+                ("k_stream", "stream.hip"), ("k_", "apply.hip"))
 
 
-def source_digest(path=None):
+def kernel_source(kernel):
+    """The csrc file that defines `kernel` (a profiler or label name)."""
+    base = kernel.replace("void ", "").replace("cast::", "").replace("(anonymous namespace)::", "")
+    for prefix, f in KERNEL_FILES:
+        if base.startswith(prefix):
+            return f
+    return "apply.hip"
+
+
+def source_digest(fname):
     import hashlib
-    return hashlib.sha256(open(path or KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(open(os.path.join(CSRC, fname), "rb").read()).hexdigest()[:16]
 
 
-def recorded_traffic(kernel):
+def digest_header():
+    """One line with the digest of every kernel source, for the summaries."""
+    files = sorted({f for _, f in KERNEL_FILES if os.path.exists(os.path.join(CSRC, f))})
+    return "# kernel_sources_sha256_16: " + ", ".join(f"{f}={source_digest(f)}" for f in files)
+
+
+def traffic_summary_path(kernel, workload="qft30_c128"):
+    stem = kernel.split("<")[0].replace("void ", "").replace("cast::", "")
+    return os.path.join(PROFILES, f"{stem}_{workload}_hbm_traffic.txt")
+
+
+def recorded_traffic(kernel, workload="qft30_c128"):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the summary is missing or the kernel source changed since."""
+    None when the summary is missing or the source that defines the kernel
+    changed since the counters were taken."""
     try:
-        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+        lines = open(traffic_summary_path(kernel, workload)).read().splitlines()
     except OSError:
         return None
-    meta = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
-    if meta.get("kernel_source_sha256_16") != source_digest():
+    digests = {}
+    for l in lines:
+        if l.startswith("# kernel_sources_sha256_16: "):
+            digests = dict(x.split("=") for x in l.split(": ", 1)[1].split(", "))
+    f = kernel_source(kernel)
+    if digests.get(f) != source_digest(f):
         return None
     for l in lines:
         if l.startswith(kernel + " |"):
@@ -659,19 +703,17 @@ def recorded_traffic(kernel):
 
 
 def summarize_kernel_trace(stats_csv, command, name_filter=None):
-    """Top kernels of a rocprofv3 --stats CSV; with name_filter, only kernels
-    whose name contains it (the digest is then that of blocked.hip for the
-    cache-blocked kernel, else of apply.hip)."""
+    """Top kernels of a rocprofv3 --stats CSV (with name_filter, only kernels
+    whose name contains it), headed by the command and the digests of the
+    kernel sources."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     if name_filter:
         rows = [r for r in rows if name_filter in r["Name"]]
-    src = os.path.join(os.path.dirname(KERNEL_SOURCE), "blocked.hip") if name_filter == "k_blocked" else None
     out = [f"# rocprofv3 kernel-trace summary" + (f" (kernels matching {name_filter})" if name_filter else ""),
-           f"# command: {command}",
-           f"# kernel_source_sha256_16: {source_digest(src)}",
+           f"# command: {command}", digest_header(),
            f"{'kernel':78s} {'calls':>6s} {'avg_ms':>9s} {'total_ms':>10s} {'min_ms':>8s} {'max_ms':>8s} {'pct':>6s}"]
-    for r in rows[:14]:
+    for r in rows[:16]:
         out.append(f"{r['Name'][:78]:78s} {int(r['Calls']):6d} {float(r['AverageNs'])/1e6:9.4f} "
                    f"{float(r['TotalDurationNs'])/1e6:10.1f} {float(r['MinNs'])/1e6:8.3f} {float(r['MaxNs'])/1e6:8.3f} "
                    f"{float(r['Percentage']):6.2f}")
@@ -702,7 +744,7 @@ def summarize_traffic(fetch_csv, write_csv, command_fetch, command_write):
     ff, wf = gib_kib / fcopy, gib_kib / wcopy
     out = ["# HBM traffic per launch from rocprofv3 PMC counters (two runs)",
            f"# command_fetch: {command_fetch}", f"# command_write: {command_write}",
-           f"# kernel_source_sha256_16: {source_digest()}",
+           digest_header(),
            f"# calibration: 1 GiB device copy reads FETCH_SIZE {fcopy:.1f} KiB (factor {ff:.4f}), "
            f"WRITE_SIZE {wcopy:.1f} KiB (factor {wf:.4f})",
            "# columns: kernel | launches | fetch_KiB_avg | write_KiB_avg | scaled_bytes_per_launch"]

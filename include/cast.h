@@ -206,6 +206,16 @@ cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t 
 cast_status fused_pass_info(const cast_fused *f, size_t i, int n, cast_dtype dt, int *kernel, int *d,
                             double *alg_bytes, double *flops);
 
+/* Streaming reference for the rooflines: multiplies `bytes` of device memory
+ * (16-byte aligned, a multiple of 16, read as doubles) in place by `factor`,
+ * each of 256 lanes per workgroup moving chunks_per_lane (1, 2, 4 or 8)
+ * 16-byte chunks per tile with non-temporal loads and stores, on at most
+ * `grid` workgroups (0: one per tile).  Every byte is read and written once
+ * and no gate work is done, so its rate is the practical ceiling of the
+ * elementwise gate kernels.  Queued on hip_stream (hipStream_t or NULL).
+ * For measurement. */
+cast_status stream_scale(void *data, size_t bytes, double factor, int chunks_per_lane, int grid, void *hip_stream);
+
 /* ------------------------------------------------------------ cache-blocked passes */
 
 /* Applies a fused list with several fused gates per HBM pass (cache

@@ -87,6 +87,8 @@ SIGNATURES = {
     "apply_circuit_jit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "apply_circuit_jit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
+    "stream_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_void_p]),
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
                                     ctypes.c_size_t, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t,
                                     _c_double_p, _c_double_p]),
