@@ -367,6 +367,23 @@ typedef struct {
  * with a fixed reduction order.  Synchronous. */
 cast_status expval(const cast_sv *sv, const cast_pauli_term *terms, size_t n_terms, double *out);
 
+/* Most terms expval_noalloc takes. */
+#define CAST_EXPVAL_NOALLOC_MAX_TERMS 4096
+
+/* expval for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result, bit for bit, from the same kernels, with the device scratch
+ * (reduction partials and per-term results, 192 KiB) in a fixed array that
+ * each GPU holds from the first call until the process ends.  Calls no
+ * hipMalloc/hipFree; on success it allocates no host memory either (fixed
+ * arrays on the stack).  n_terms above
+ * CAST_EXPVAL_NOALLOC_MAX_TERMS is CAST_EINVAL.  The state must be on the
+ * current HIP device.  All calls on one GPU share its array, so calls that
+ * overlap on one GPU (other threads, or work queued on other streams) race;
+ * the call is synchronous, so consecutive calls from one thread do not.
+ * Synchronous. */
+cast_status expval_noalloc(const cast_sv *sv, const cast_pauli_term *terms, size_t n_terms, double *out);
+
 /* ------------------------------------------------------------ gradients */
 
 /* Energy and adjoint-method gradient (Jones & Gacon 2020) of

@@ -87,6 +87,7 @@ SIGNATURES = {
     "apply_circuit_jit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "apply_circuit_jit_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
     "expval": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
+    "expval_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_pauli_term), ctypes.c_size_t, _c_double_p]),
     "stream_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_void_p]),
     "adjoint_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(cast_gate), ctypes.c_size_t, _c_double_p,
@@ -478,6 +479,14 @@ class StateVector:
         arr = pauli_terms(terms)
         out = np.zeros(2)
         expval(self.handle, arr, len(terms), _dptr(out))
+        return complex(out[0], out[1])
+
+    def expval_noalloc(self, terms):
+        """expval with the device scratch in the library's fixed array (no
+        device allocation; at most CAST_EXPVAL_NOALLOC_MAX_TERMS terms)."""
+        arr = pauli_terms(terms)
+        out = np.zeros(2)
+        expval_noalloc(self.handle, arr, len(terms), _dptr(out))
         return complex(out[0], out[1])
 
     def numpy(self):
