@@ -51,7 +51,8 @@ def kernel_label(info, dtype_name):
     kind, d = info["kernel"], info.get("d", 0)
     r = "double" if dtype_name == "c128" else "float"
     if kind == 6:
-        return f"k_diag_run<{r}, {cast.get_tuning('diag_run_unroll', dt)}, {info['tables']}>"
+        lds = "true" if cast.get_tuning("diag_run_lds", dt) else "false"
+        return f"k_diag_run<{r}, {cast.get_tuning('diag_run_unroll', dt)}, {info['tables']}, {lds}>"
     if kind == 3:
         lds = "true" if cast.get_tuning("diag_lds_table", dt) else "false"
         return f"k_diag<{r}, {cast.get_tuning('diag_unroll', dt)}, {lds}>"
@@ -63,7 +64,8 @@ def kernel_label(info, dtype_name):
         return f"k_direct<{d}, {r}, {ipt}, {nt}>"
     m3 = "true" if d >= cast.get_tuning("mfma_3m_min_d", dt) else "false"
     if kind == 4:
-        return f"k_mfma_direct<{d}, {r}, {m3}>"
+        pre = "true" if cast.get_tuning("mfma_prefetch", dt) else "false"
+        return f"k_mfma_direct<{d}, {r}, {m3}, {pre}>"
     if kind == 5:
         return f"k_mfma_tile<{d}, {r}, {m3}>"
     two = "true" if kind == 2 else "false"
@@ -169,16 +171,29 @@ def qft_c64_error(n, k_max, seed=5):
 
 def copy_bandwidth(gib=4, reps=5):
     """Streaming rate on this GPU (bytes read + written per second, HIP
-    events): the better of a device-to-device copy and an in-place scale of a
-    `gib` GiB buffer, best of `reps` each.  The practical streaming ceiling
-    the roofline fraction is also quoted against."""
+    events): a device-to-device copy and an in-place scale of a `gib` GiB
+    buffer by torch, and the library's streaming reference kernel
+    (stream_scale: 16 bytes per lane, 1/2/4/8 chunks in flight per lane,
+    non-temporal) on the same buffer; best of `reps` each.  Returns the best
+    rate, its kind, and every rate measured."""
+    import ctypes
+
     import torch
+
+    import paper_2503_19894_amd as cast
 
     n = (gib << 30) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def kernel(u):
+        return lambda: cast.stream_scale(ctypes.c_void_p(src.data_ptr()), n * 8, 1.0, u, 0, stream)
+
+    ops = [("copy", lambda: dst.copy_(src)), ("in-place scale", lambda: src.mul_(1.0))]
+    ops += [(f"stream kernel x{u}", kernel(u)) for u in (1, 2, 4, 8)]
     best = {}
-    for kind, op in (("copy", lambda: dst.copy_(src)), ("in-place scale", lambda: src.mul_(1.0))):
+    for kind, op in ops:
         op()
         t = float("inf")
         for _ in range(reps):
@@ -188,11 +203,11 @@ def copy_bandwidth(gib=4, reps=5):
             b.record()
             b.synchronize()
             t = min(t, a.elapsed_time(b))
-        best[kind] = 2.0 * (gib << 30) / (t * 1e-3) / 1e9
+        best[kind] = round(2.0 * (gib << 30) / (t * 1e-3) / 1e9, 1)
     del src, dst
     torch.cuda.empty_cache()
     kind = max(best, key=best.get)
-    return best[kind], kind
+    return best[kind], kind, best
 
 
 def run_families(n=30, dtype_names=("c128", "c64")):
@@ -572,6 +587,27 @@ def run_vqa(sets=256, n=20, layers=8, steps=2, warmup=1, plain_sets=8, oracle_ch
     return out
 
 
+def run_vqa_profile(sets=256, n=20, layers=8):
+    """One complex128 batch of the VQA workload in graph mode after one
+    warm-up run: the command the batched kernels are profiled with."""
+    import torch
+
+    import paper_2503_19894_amd as cast
+    from circuits import hea_vqa, vqa_hamiltonian, vqa_thetas
+
+    gates, P = hea_vqa(n, layers)
+    H = vqa_hamiltonian(n)
+    th = vqa_thetas(P, sets, seed=0)
+    b = cast.Batch([gates] * sets, [n] * sets, [P] * sets, [H] * sets, dtype=torch.complex128,
+                   mode=cast.BATCH_STEPS_GRAPH)
+    b.run(list(th))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(list(th))
+    wall = time.perf_counter() - t0
+    return {"sets": sets, "s_per_batch": wall, "grads_per_s": sets / wall, **b.info(), **b.traffic()}
+
+
 def vqa_summary(vqa):
     """Headline figures of the batched VQA measurement: grads/s batched (best
     mode) and plain, both dtypes, and the batched run's roofline: algorithmic
@@ -770,6 +806,8 @@ def main():
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-vqa", action="store_true")
     ap.add_argument("--vqa-only", action="store_true", help="only the batched VQA measurement")
+    ap.add_argument("--vqa-profile", action="store_true",
+                    help="only one complex128 VQA batch in graph mode (the profiled command)")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-tfim", action="store_true")
     ap.add_argument("--tfim-only", action="store_true", help="only the mixed-size TFIM batch")
@@ -815,6 +853,9 @@ def main():
     if args.dense_only:
         print(json.dumps(run_dense()), flush=True)
         return
+    if args.vqa_profile:
+        print(json.dumps(run_vqa_profile()), flush=True)
+        return
     if args.vqa_only:
         print(json.dumps(run_vqa(oracle_check=False)), flush=True)
         return
@@ -847,12 +888,12 @@ def main():
     c64_err = None if args.no_c64 else qft_c64_error(args.n, args.k_max)
     dom = main_run["kernels"][main_run["dominant"]]
     traffic = recorded_traffic(main_run["dominant"])
-    copy_gbs, copy_kind = copy_bandwidth()
+    copy_gbs, copy_kind, copy_all = copy_bandwidth()
     roof = {"bound": "hbm", "kernel": main_run["dominant"], "achieved": round(dom["achieved_gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_launch_ms": round(dom["avg_launch_ms"], 4),
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
-            "copy_gbs": round(copy_gbs, 1), "copy_kind": copy_kind,
+            "copy_gbs": round(copy_gbs, 1), "copy_kind": copy_kind, "streaming_rates_gbs": copy_all,
             "frac_of_copy": round(dom["achieved_gbs"] / copy_gbs, 4)}
     if traffic:
         # HBM bytes actually moved per launch over the launch time, against the copy rate

@@ -446,6 +446,19 @@ cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items,
  * count two).  Either output may be NULL. */
 cast_status batch_traffic(const cast_batch *b, double *alg_bytes, uint64_t *state_passes);
 
+/* The segments batch_create cuts one instance's gate list into (host only,
+ * no device work): gates whose qubits together fit one LDS tile of 2^tb
+ * amplitudes (tb = min(n, 11) for CAST_C128, min(n, 12) for CAST_C64), at
+ * most 64 gates each, forward (reverse = 0) or for the reverse adjoint sweep
+ * (reverse = 1).  Segments may take gates out of circuit order: two gates
+ * that share a qubit keep their relative order unless both are diagonal;
+ * gates on disjoint qubits commute (CAST_BATCH_REORDER=0 in the environment
+ * keeps the circuit order).  *n_segments receives the count; if not NULL,
+ * order[i] (n_gates entries) receives the i-th gate applied and
+ * segment_of[i] its segment.  Gates are validated as in batch_create. */
+cast_status batch_segments(int n, const cast_gate *gates, size_t n_gates, cast_dtype dt, int reverse,
+                           size_t *n_segments, int *order, int *segment_of);
+
 void batch_destroy(cast_batch *b);
 
 /* batch_create + batch_run + batch_destroy in one call. */

@@ -102,6 +102,9 @@ SIGNATURES = {
                                  ctypes.POINTER(_c_double_p)]),
     "batch_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_uint64), _c_double_p]),
     "batch_traffic": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "batch_segments": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(cast_gate), ctypes.c_size_t, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
     "batch_destroy": (None, [ctypes.c_void_p]),
     "tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int]),
     "tuning_get": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, _c_int_p]),
@@ -239,7 +242,8 @@ def fusion_options(k_max=5, opcount_cap=0.0, zero_tol=1e-14, one_tol=1e-14, aggl
 TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "direct_chunk_log", "max_grid", "use_diag", "mfma_min_d",
                "mfma_grid_per_cu", "mfma_direct_min_q", "diag_unroll", "diag_max_grid", "diag_lds_table",
                "diag_order", "blocked_tile_bits", "blocked_threads", "mfma_3m_min_d", "mfma_low_tile",
-               "persistent_spin_limit", "diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid")
+               "persistent_spin_limit", "diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid",
+               "diag_run_lds", "mfma_prefetch", "diag_spread")
 PATH_COST_KEYS = tuple(f"bw{i}" for i in range(7)) + ("fl4", "fl5", "fl6", "fl_vec", "launch_ms", "seg_bw") + \
     tuple(f"seg_gate{d}" for d in range(4))
 #: environment overrides (set for sweeps) take precedence over the tuning file
@@ -571,6 +575,21 @@ class Batch:
         if getattr(self, "handle", None):
             _destroy(self.handle)
             self.handle = None
+
+
+def segments(n, gates, dtype=torch.complex128, reverse=False):
+    """The segments batch_create cuts a batched instance's gate list into:
+    a list of segments, each the gate indices it applies in order."""
+    ga = GateArray(gates)
+    cnt = ctypes.c_size_t()
+    order = (ctypes.c_int * max(1, ga.n))()
+    seg = (ctypes.c_int * max(1, ga.n))()
+    batch_segments(n, ga.arr, ga.n, C128 if dtype == torch.complex128 else C64, int(reverse), ctypes.byref(cnt),
+                   order, seg)
+    out = [[] for _ in range(cnt.value)]
+    for i in range(ga.n):
+        out[seg[i]].append(order[i])
+    return out
 
 
 class CircuitEnergy(torch.autograd.Function):

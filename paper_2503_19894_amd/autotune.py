@@ -42,6 +42,10 @@ KNOB_CHOICES = [
     ("mfma_3m_min_d", [4, 5, 6, 7]),
     ("mfma_low_tile", [0, 1]),
     ("direct_chunk_log", [6, 8, 10, 12]),
+    ("diag_run_unroll", [1, 2, 4]),
+    ("diag_run_grid", [1 << 12, 1 << 16, 1 << 20]),
+    ("diag_run_lds", [0, 1]),
+    ("mfma_prefetch", [0, 1]),
 ]
 
 

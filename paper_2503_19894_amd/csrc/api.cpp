@@ -523,6 +523,9 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "diag_run_qubits") { *lo = 4; *hi = kRunMaxQ; return &t.diag_run_qubits[i]; }
     if (key == "diag_run_unroll") { *lo = 1; *hi = 4; return &t.diag_run_unroll[i]; }
     if (key == "diag_run_grid") { *lo = 256; return &t.diag_run_grid[i]; }
+    if (key == "diag_run_lds") { *hi = 1; return &t.diag_run_lds[i]; }
+    if (key == "mfma_prefetch") { *hi = 1; return &t.mfma_prefetch[i]; }
+    if (key == "diag_spread") { *hi = 1; return &t.diag_spread[i]; }
     return nullptr;
 }
 

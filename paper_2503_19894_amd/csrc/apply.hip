@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
 #pragma unroll
     for (int h = 0; h < A; ++h) jl[h] = jof(((uint64_t)threadIdx.x << S) | (uint64_t)h);
     constexpr uint64_t per = 256ull * U;
-    const bool spread = (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
+    const bool spread = a.spread && (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
     for (uint64_t it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const uint32_t t = (uint32_t)(spread ? xcd_spread(it) : it);   // ntiles <= 2^24
         uint32_t rest, pat;
@@ -497,7 +497,10 @@ __device__ __forceinline__ void stage_blocks(V *mt, const R *mat, uint32_t nblk)
 // complex product (Gauss; the "3M method" for complex matrix products):
 // P = Ur Xr, Q = Ui Xi, S = (Ur + Ui)(Xr + Xi), then Yr = P - Q and
 // Yi = S - P - Q, one matrix-core product fewer per k-step.
-template <int D, typename R, bool M3, typename Load, typename Store>
+// PRE: the unit's 2^d / 4 input loads per lane are all issued before the
+// first matrix-core product instead of one k-step ahead, so a wave waits on
+// memory once per unit rather than repeatedly inside the product chain.
+template <int D, typename R, bool M3, typename Load, typename Store, bool PRE = false>
 __device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load load, Store store) {
     using V = typename Amp<R>::T;
     using M = Mfma<R>;
@@ -512,10 +515,16 @@ __device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load
             if (M3) cs[t][v] = 0;
         }
     }
-#pragma unroll 4
+    V xs[PRE ? N / 4 : 1];
+    if (PRE) {
+#pragma unroll
+        for (int s = 0; s < N / 4; ++s) xs[PRE ? s : 0] = load(4 * s + kk);
+    }
+    constexpr int UNR = PRE ? N / 4 : 4;
+#pragma unroll UNR
     for (int s = 0; s < N / 4; ++s) {
         const int c = 4 * s + kk;
-        const V x = load(c);
+        const V x = PRE ? xs[PRE ? s : 0] : load(c);
         const V *col = mt_blk + c * N + j;
         if (M3) {
             const R xs = x.x + x.y;
@@ -563,7 +572,7 @@ __device__ __forceinline__ uint64_t off_of(const uint64_t *off, int c) {
     return o;
 }
 
-template <int D, typename R, bool M3>
+template <int D, typename R, bool M3, bool PRE>
 __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, const R *__restrict__ mat, PassArgs a) {
     using V = typename Amp<R>::T;
     constexpr int N = 1 << D;
@@ -586,9 +595,9 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
         uint64_t base = deposit(g, a.lowmask, a.k);
         for (int q = 0; q < a.k - D; ++q)
             if ((bid >> q) & 1u) base ^= a.off[D + q];
-        mfma_unit<D, R, M3>(
-            mt + (size_t)bs * N * N, [&](int c) { return psi[base ^ off_of<D>(a.off, c)]; },
-            [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; });
+        auto ld = [&](int c) { return psi[base ^ off_of<D>(a.off, c)]; };
+        auto st = [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; };
+        mfma_unit<D, R, M3, decltype(ld), decltype(st), PRE>(mt + (size_t)bs * N * N, ld, st);
     }
 }
 
@@ -815,25 +824,29 @@ bool mfma_fits(int n, cast_dtype dt, const PassPlan &p) {
 }
 
 template <typename R>
-static hipError_t launch_mfma(int D, bool tile, bool m3, R *psi, const R *m, const PassArgs &a, int grid,
+static hipError_t launch_mfma(int D, bool tile, bool m3, bool pre, R *psi, const R *m, const PassArgs &a, int grid,
                               size_t lds, hipStream_t s) {
-#define CAST_MFMA_K(KERN, DD, M3)                                                                        \
+#define CAST_MFMA_K(KERN, ...)                                                                           \
     {                                                                                                    \
         static bool set = false;                                                                         \
         if (!set) {                                                                                      \
-            hipError_t e = hipFuncSetAttribute((const void *)KERN<DD, R, M3>,                            \
+            hipError_t e = hipFuncSetAttribute((const void *)KERN<__VA_ARGS__>,                          \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 128 << 10);   \
             if (e != hipSuccess) return e;                                                               \
             set = true;                                                                                  \
         }                                                                                                \
-        hipLaunchKernelGGL((KERN<DD, R, M3>), dim3(grid), dim3(256), lds, s, psi, m, a);                 \
+        hipLaunchKernelGGL((KERN<__VA_ARGS__>), dim3(grid), dim3(256), lds, s, psi, m, a);               \
     }
 #define CAST_MFMA(DD)                                                                                    \
     case DD:                                                                                             \
         if (tile) {                                                                                      \
-            if (m3) CAST_MFMA_K(k_mfma_tile, DD, true) else CAST_MFMA_K(k_mfma_tile, DD, false)         \
+            if (m3) CAST_MFMA_K(k_mfma_tile, DD, R, true) else CAST_MFMA_K(k_mfma_tile, DD, R, false)   \
+        } else if (pre) {                                                                                \
+            if (m3) CAST_MFMA_K(k_mfma_direct, DD, R, true, true)                                       \
+            else CAST_MFMA_K(k_mfma_direct, DD, R, false, true)                                          \
         } else {                                                                                         \
-            if (m3) CAST_MFMA_K(k_mfma_direct, DD, true) else CAST_MFMA_K(k_mfma_direct, DD, false)     \
+            if (m3) CAST_MFMA_K(k_mfma_direct, DD, R, true, false)                                      \
+            else CAST_MFMA_K(k_mfma_direct, DD, R, false, false)                                         \
         }                                                                                                \
         break;
     switch (D) {
@@ -901,10 +914,12 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             lds += ((size_t)1 << tb) * amp_bytes(dt);
         }
         if (dt == CAST_C128)
-            e = launch_mfma<double>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], (double *)psi, (const double *)dmat, a,
+            e = launch_mfma<double>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt] != 0, (double *)psi,
+                                    (const double *)dmat, a,
                                     (int)grid, lds, stream);
         else
-            e = launch_mfma<float>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], (float *)psi, (const float *)dmat, a,
+            e = launch_mfma<float>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt] != 0, (float *)psi,
+                                   (const float *)dmat, a,
                                    (int)grid, lds, stream);
     } else if (kind == 3) {
         DiagArgs g;
@@ -939,6 +954,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             for (int j = 0; j < nrel; ++j) g.hlowmask[j] = (1ull << (p.q[kl + rel[j]] - tb)) - 1;
             g.rest_bits = (n - tb) - nrel;
             g.pattern_major = tu.diag_order[dt];
+            g.spread = tu.diag_spread[dt];
             int npat = 0;
             for (uint32_t pr = 0; pr < (1u << nrel); ++pr) {
                 uint32_t ph = 0, off = 0;

@@ -192,6 +192,114 @@ static void free_batch(cast_batch *b) {
     delete b;
 }
 
+// Tile of a segment: 2^11 complex128 or 2^12 complex64 amplitudes (psi and
+// lambda together 64 KiB of LDS); CAST_BATCH_TILE_BITS overrides.
+static int batch_tile_bits(cast_dtype dt) {
+    int tb = dt == CAST_C128 ? 11 : 12;
+    if (const char *e = std::getenv("CAST_BATCH_TILE_BITS")) tb = std::min(12, std::max(4, atoi(e)));
+    return tb;
+}
+
+// Whether segments may take gates out of circuit order (CAST_BATCH_REORDER=0
+// keeps the circuit order).
+static bool batch_reorder() {
+    const char *e = std::getenv("CAST_BATCH_REORDER");
+    return !e || atoi(e) != 0;
+}
+
+// Cuts a gate list into segments whose qubits fit a tile of 2^tb amplitudes
+// (at most kSegMaxGates gates each), returned in application order: the
+// circuit's order (reverse: the reverse order) or, with `reorder`, another
+// order of the same circuit.  Two gates that share a qubit keep their
+// relative order unless both are diagonal (diagonal gates commute); gates on
+// disjoint qubits commute.  So any order in which every such pair keeps its
+// relative order applies the same operator, and the adjoint sweep evaluates
+// each gate's derivative between the states that order gives before and
+// after it.  The greedy schedule fills a segment with ready gates (all
+// earlier dependent gates applied), preferring those whose qubits the
+// segment already holds, then the earliest ready gate that still fits.  On
+// a layered ansatz (rotations on every qubit, then an entangling ring) this
+// roughly halves the segments of the circuit-order cut, since a layer's
+// rotations on the qubits of one tile need not wait for the rest of the
+// layer.
+static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &gmask, const std::vector<char> &gdiag,
+                                                   int tb, bool reverse, bool reorder) {
+    const int L = (int)gmask.size();
+    auto gate_at = [&](int p) { return reverse ? L - 1 - p : p; };   // base order position -> gate
+    std::vector<std::vector<int>> segs;
+    if (!reorder) {
+        std::vector<int> cur;
+        uint64_t qm = 0;
+        for (int p = 0; p < L; ++p) {
+            const int l = gate_at(p);
+            if (!cur.empty() && (__builtin_popcountll(qm | gmask[l]) > tb || cur.size() >= (size_t)kSegMaxGates)) {
+                segs.push_back(cur);
+                cur.clear();
+                qm = 0;
+            }
+            cur.push_back(l);
+            qm |= gmask[l];
+        }
+        if (!cur.empty()) segs.push_back(cur);
+        return segs;
+    }
+    // dependence graph over base positions: per qubit, the last non-diagonal
+    // gate and the diagonal gates since it
+    std::vector<std::vector<int>> succ(L);
+    std::vector<int> indeg(L, 0);
+    std::vector<int> last_nd(64, -1);
+    std::vector<std::vector<int>> diag_since(64);
+    auto edge = [&](int a, int b) {
+        if (a < 0) return;
+        succ[a].push_back(b);
+        ++indeg[b];
+    };
+    for (int p = 0; p < L; ++p) {
+        const int l = gate_at(p);
+        std::vector<int> preds;
+        for (int q = 0; q < 64; ++q) {
+            if (!((gmask[l] >> q) & 1ull)) continue;
+            if (gdiag[l]) {
+                preds.push_back(last_nd[q]);
+                diag_since[q].push_back(p);
+            } else {
+                preds.push_back(last_nd[q]);
+                for (int d : diag_since[q]) preds.push_back(d);
+                diag_since[q].clear();
+                last_nd[q] = p;
+            }
+        }
+        std::sort(preds.begin(), preds.end());
+        preds.erase(std::unique(preds.begin(), preds.end()), preds.end());
+        for (int a : preds) edge(a, p);
+    }
+    std::vector<int> ready;   // base positions, ascending
+    for (int p = 0; p < L; ++p)
+        if (!indeg[p]) ready.push_back(p);
+    int done = 0;
+    while (done < L) {
+        std::vector<int> cur;
+        uint64_t qm = 0;
+        while (cur.size() < (size_t)kSegMaxGates && !ready.empty()) {
+            int pick = -1;
+            for (size_t r = 0; r < ready.size() && pick < 0; ++r)
+                if (!(gmask[gate_at(ready[r])] & ~qm)) pick = (int)r;
+            for (size_t r = 0; r < ready.size() && pick < 0; ++r)
+                if (__builtin_popcountll(qm | gmask[gate_at(ready[r])]) <= tb) pick = (int)r;
+            if (pick < 0) break;
+            const int p = ready[pick];
+            ready.erase(ready.begin() + pick);
+            cur.push_back(gate_at(p));
+            qm |= gmask[gate_at(p)];
+            ++done;
+            for (int b : succ[p])
+                if (--indeg[b] == 0) ready.insert(std::lower_bound(ready.begin(), ready.end(), b), b);
+        }
+        segs.push_back(cur);
+    }
+    return segs;
+}
+
 template <typename T>
 static cast_status upload(T **dst, const std::vector<T> &src) {
     if (cast_status rc = dev_alloc((void **)dst, std::max<size_t>(1, src.size()) * sizeof(T))) return rc;
@@ -228,13 +336,14 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     // amplitudes per work item, and the cache budget of an instance group
     // tile of a segment: 2^11 complex128 or 2^12 complex64 amplitudes, psi
     // and lambda together 64 KiB of LDS
-    int tile_bits = dt == CAST_C128 ? 11 : 12;
-    if (const char *e = std::getenv("CAST_BATCH_TILE_BITS")) tile_bits = std::min(12, std::max(4, atoi(e)));
+    const int tile_bits = batch_tile_bits(dt);
     // per-step launches: groups sized for the 256 MB last-level cache; the
     // persistent launch keeps every instance in one step-major stream
     double group_bytes = mode == 2 ? 0.0 : 192.0 * (1 << 20);
     if (const char *e = std::getenv("CAST_BATCH_GROUP_MB"))
         if (mode != 2) group_bytes = atof(e) * (1 << 20);
+    if (const char *e = std::getenv("CAST_PERSISTENT_GROUP_MB"))
+        if (mode == 2) group_bytes = atof(e) * (1 << 20);
     uint64_t mat_entries = 0, part = 0, res = 0;
     auto bail = [&](cast_status rc) {
         free_batch(b);
@@ -320,28 +429,16 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
             mat_entries += (uint64_t)D * D;
         }
         ip.nslots = slot;
-        // segments: consecutive gates (forward order, then reverse order)
-        // whose qubits together fit one tile of 2^tb amplitudes
+        // segments (forward order, then reverse order) whose qubits together
+        // fit one tile of 2^tb amplitudes
         ip.tb = std::min(n, tile_bits);
-        auto segment = [&](bool reverse) {
-            std::vector<std::vector<int>> segs;
-            std::vector<int> cur;
-            uint64_t qm = 0;
-            for (size_t c = 0; c < L; ++c) {
-                const int l = reverse ? (int)(L - 1 - c) : (int)c;
-                uint64_t gm = 0;
-                for (int a = 0; a < ip.gates[l].k; ++a) gm |= 1ull << ip.gates[l].qubits[a];
-                if (!cur.empty() && (__builtin_popcountll(qm | gm) > ip.tb || cur.size() >= (size_t)kSegMaxGates)) {
-                    segs.push_back(cur);
-                    cur.clear();
-                    qm = 0;
-                }
-                cur.push_back(l);
-                qm |= gm;
-            }
-            if (!cur.empty()) segs.push_back(cur);
-            return segs;
-        };
+        std::vector<uint64_t> gmask(L, 0);
+        std::vector<char> gdiag(L, 0);
+        for (size_t l = 0; l < L; ++l) {
+            for (int a = 0; a < ip.gates[l].k; ++a) gmask[l] |= 1ull << ip.gates[l].qubits[a];
+            gdiag[l] = ip.form[l] == BF_DIAG;
+        }
+        auto segment = [&](bool reverse) { return segment_gates(gmask, gdiag, ip.tb, reverse, batch_reorder()); };
         for (auto &sg : segment(false)) {
             ip.ops.push_back(HostOp{BK_FWD, -1, -1});
             ip.seg_gates.push_back(sg);
@@ -703,6 +800,49 @@ cast_status batch_info(const cast_batch *b, int *n_steps, uint64_t *total_items,
         for (auto &ip : b->inst) s += 2.0 * std::ldexp(1.0, ip.n) * (double)amp_bytes(b->dt);
         *state_bytes = s;
     }
+    return CAST_OK;
+}
+
+cast_status batch_segments(int n, const cast_gate *gates, size_t n_gates, cast_dtype dt, int reverse,
+                           size_t *n_segments, int *order, int *segment_of) {
+    if (!n_segments) return fail(CAST_EINVAL, "n_segments is NULL");
+    if (n_gates && !gates) return fail(CAST_EINVAL, "gates is NULL");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n < 3 || n > kMaxQubits) return fail(CAST_EINVAL, "qubit count must be in [3, 34]");
+    std::vector<uint64_t> gmask(n_gates, 0);
+    std::vector<char> gdiag(n_gates, 0);
+    for (size_t l = 0; l < n_gates; ++l) {
+        const cast_gate &g = gates[l];
+        if (g.k < 1 || g.k > 2) return fail(CAST_EUNSUPPORTED, "batched programs take 1- and 2-qubit gates");
+        for (int a = 0; a < g.k; ++a) {
+            if (g.qubits[a] < 0 || g.qubits[a] >= n) return fail(CAST_EINVAL, "gate qubit out of range");
+            gmask[l] |= 1ull << g.qubits[a];
+        }
+        bool diag = true;
+        if (g.param_id >= 0) {
+            for (int a = 0; a < g.k; ++a) {
+                const int letter = (g.generator >> (2 * a)) & 3;
+                if (letter == 1 || letter == 2) diag = false;
+            }
+        } else {
+            if (!g.matrix) return fail(CAST_EINVAL, "fixed gate without a matrix");
+            const int D = 1 << g.k;
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c)
+                    if (r != c && (g.matrix[2 * (r * D + c)] != 0.0 || g.matrix[2 * (r * D + c) + 1] != 0.0)) diag = false;
+        }
+        gdiag[l] = diag;
+    }
+    const std::vector<std::vector<int>> segs =
+        segment_gates(gmask, gdiag, std::min(n, batch_tile_bits(dt)), reverse != 0, batch_reorder());
+    *n_segments = segs.size();
+    size_t i = 0;
+    for (size_t sgi = 0; sgi < segs.size(); ++sgi)
+        for (int l : segs[sgi]) {
+            if (order) order[i] = l;
+            if (segment_of) segment_of[i] = (int)sgi;
+            ++i;
+        }
     return CAST_OK;
 }
 

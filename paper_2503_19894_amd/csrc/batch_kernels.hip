@@ -23,6 +23,16 @@ __device__ __forceinline__ uint64_t ins0(uint64_t g, int q) {
     return ((g & ~lm) << 1) | (g & lm);
 }
 
+// The read-only tables (gate matrices, gate and sweep records) are read
+// through the constant address space.  Nothing in a kernel writes them, so
+// their loads may use the scalar cache and land in SGPRs.  Through generic
+// pointers the compiler must assume that the kernel's own stores to the
+// states may alias them, and in a loop over work items (the persistent
+// launch) every such load after the first item's stores became a vector load
+// into VGPRs: 223 VGPRs instead of 119 for complex128.
+template <typename T> using CPtr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ __forceinline__ CPtr<T> cptr(const T *p) { return (CPtr<T>)p; }
+
 template <typename V, typename R>
 __device__ __forceinline__ V cmul_acc(V acc, R mr, R mi, V v) {
     acc.x = fma(mr, v.x, acc.x);
@@ -34,7 +44,7 @@ __device__ __forceinline__ V cmul_acc(V acc, R mr, R mi, V v) {
 
 // y = M x for a 2^K-vector held in registers (M row-major, uniform).
 template <int K, typename V, typename R>
-__device__ __forceinline__ void small_matvec(const R *m, const V *x, V *y) {
+__device__ __forceinline__ void small_matvec(CPtr<R> m, const V *x, V *y) {
     constexpr int D = 1 << K;
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -62,7 +72,7 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // tile bits.  Bit positions are template parameters so every register index
 // is a compile-time constant.
 template <int B, typename V, typename R>
-__device__ __forceinline__ void reg_apply1(V *x, const R *m) {
+__device__ __forceinline__ void reg_apply1(V *x, CPtr<R> m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j & (1 << B)) continue;
@@ -80,7 +90,7 @@ __device__ __forceinline__ void reg_apply1(V *x, const R *m) {
 }
 
 template <int B0, int B1, typename V, typename R>
-__device__ __forceinline__ void reg_apply2(V *x, const R *m) {
+__device__ __forceinline__ void reg_apply2(V *x, CPtr<R> m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
@@ -96,7 +106,7 @@ __device__ __forceinline__ void reg_apply2(V *x, const R *m) {
 
 // Diagonal gate on sweep bits (B0, B1; B1 < 0 for one qubit): x[j] *= D[j's bits].
 template <int B0, int B1, typename V, typename R>
-__device__ __forceinline__ void reg_diag(V *x, const R *m) {
+__device__ __forceinline__ void reg_diag(V *x, CPtr<R> m) {
     constexpr int K = B1 < 0 ? 1 : 2, DIM = 1 << K;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -110,7 +120,7 @@ __device__ __forceinline__ void reg_diag(V *x, const R *m) {
 
 // Real matrix: only the real parts of the entries are read (two multiplies per entry).
 template <int B, typename V, typename R>
-__device__ __forceinline__ void reg_real1(V *x, const R *m) {
+__device__ __forceinline__ void reg_real1(V *x, CPtr<R> m) {
     const R m00 = m[0], m01 = m[2], m10 = m[4], m11 = m[6];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -125,7 +135,7 @@ __device__ __forceinline__ void reg_real1(V *x, const R *m) {
 }
 
 template <int B0, int B1, typename V, typename R>
-__device__ __forceinline__ void reg_real2(V *x, const R *m) {
+__device__ __forceinline__ void reg_real2(V *x, CPtr<R> m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j & ((1 << B0) | (1 << B1))) continue;
@@ -148,7 +158,7 @@ __device__ __forceinline__ void reg_real2(V *x, const R *m) {
 }
 
 template <typename V, typename R>
-__device__ __forceinline__ void reg_apply(const SegGate &G, V *x, const R *m) {
+__device__ __forceinline__ void reg_apply(const SegGate &G, V *x, CPtr<R> m) {
     if (G.form == BF_DIAG) {
         if (G.k == 1) {
             switch (G.t0) {
@@ -226,6 +236,49 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
+__device__ __forceinline__ SegSweep load_sweep(CPtr<SegSweep> p) {
+    SegSweep w;
+    w.b[0] = p->b[0];
+    w.b[1] = p->b[1];
+    w.b[2] = p->b[2];
+    w.g0 = p->g0;
+    w.g1 = p->g1;
+    w.p0 = p->p0;
+    return w;
+}
+
+__device__ __forceinline__ SegGate load_gate(CPtr<SegGate> p) {
+    SegGate g;
+    g.k = p->k;
+    g.t0 = p->t0;
+    g.t1 = p->t1;
+    g.slot = p->slot;
+    g.xl = p->xl;
+    g.zl = p->zl;
+    g.mat = p->mat;
+    g.form = p->form;
+    g.pad = 0;
+    return g;
+}
+
+__device__ __forceinline__ BatchInst load_inst(CPtr<BatchInst> p) {
+    BatchInst b;
+    b.psi = p->psi;
+    b.lam = p->lam;
+    b.n = p->n;
+    b.nslots = p->nslots;
+    b.wgs = p->wgs;
+    b.ngroups = p->ngroups;
+    b.part_off = p->part_off;
+    b.res_off = p->res_off;
+    b.tg_off = p->tg_off;
+    b.tt_off = p->tt_off;
+    b.init_kind = p->init_kind;
+    b.pad = 0;
+    b.init_src = p->init_src;
+    return b;
+}
+
 // LDS position of tile amplitude e: 16-byte chunk c is stored at chunk
 // c ^ hash(c / 16), which keeps the coalesced load/store phases conflict-free
 // and spreads the sweeps' power-of-two-strided group reads over the banks.
@@ -240,47 +293,50 @@ __device__ __forceinline__ uint32_t bat(uint32_t e) { return (bswz(e >> S) << S)
 // amplitudes each, swizzled as above.  A forward step's launch carries one
 // tile's LDS, so more of its workgroups share a compute unit.
 template <typename R>
-__device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst &in, uint32_t w, double *red,
+__device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst &in, uint32_t w, double *red,
                          typename BAmp<R>::T *lds) {
     using V = typename BAmp<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;      // log2(amplitudes per 16-byte chunk)
-    const bool adj = rec.kind == BK_ADJ;
-    const uint32_t T = 1u << rec.tb;
+    const bool adj = rec->kind == BK_ADJ;
+    const uint32_t T = 1u << rec->tb;
     uint64_t *hid = reinterpret_cast<uint64_t *>(lds);            // [2][64]
     double *gsum = reinterpret_cast<double *>(hid + 128);         // [kSegMaxGates][4 waves][2]
     V *tp = reinterpret_cast<V *>(reinterpret_cast<char *>(lds) + kSegLdsExtra), *tl = tp + T;
     V *psi = reinterpret_cast<V *>(in.psi);
     V *lam = reinterpret_cast<V *>(in.lam);
-    uint64_t tbase = (uint64_t)w << rec.W;
-    for (int j = 0; j < rec.khi; ++j) tbase = ins0(tbase, rec.qhi[j]);
+    uint64_t tbase = (uint64_t)w << rec->W;
+    for (int j = 0; j < rec->khi; ++j) tbase = ins0(tbase, rec->qhi[j]);
     for (int i = threadIdx.x; i < kSegMaxGates * 4 * 2; i += blockDim.x) gsum[i] = 0.0;
     if (threadIdx.x < 128) {
         const uint32_t h = threadIdx.x >> 6, r = threadIdx.x & 63;
         uint64_t x = 0;
         for (int j = 0; j < 6; ++j) {
             const int bit = 6 * (int)h + j;
-            if (bit < rec.khi && ((r >> j) & 1u)) x |= 1ull << rec.qhi[bit];
+            if (bit < rec->khi && ((r >> j) & 1u)) x |= 1ull << rec->qhi[bit];
         }
         hid[threadIdx.x] = x;
     }
     __syncthreads();
     // 16-byte chunks of the tile (a run holds at least one chunk when W >= S)
-    const bool chunked = rec.W >= S;
+    const bool chunked = rec->W >= S;
     const uint32_t nchunk = chunked ? (T >> S) : T;
-    const uint32_t wmask = (1u << rec.W) - 1;
+    const uint32_t wmask = (1u << rec->W) - 1;
     auto addr = [&](uint32_t e) {
-        const uint32_t r = e >> rec.W;
+        const uint32_t r = e >> rec->W;
         return tbase | (e & wmask) | hid[r & 63] | hid[64 + (r >> 6)];
     };
     if (chunked) {
-        // four chunks of each state in flight per lane
+        // eight chunks of each state in flight per lane (a whole 2^11-amplitude
+        // complex128 or 2^12-amplitude complex64 tile per 256 lanes): the item
+        // waits on its loads once instead of twice
+        constexpr int DEPTH = 8;
         typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
         nu4 *t16p = reinterpret_cast<nu4 *>(tp), *t16l = reinterpret_cast<nu4 *>(tl);
         const nu4 *p16 = reinterpret_cast<const nu4 *>(psi), *l16 = reinterpret_cast<const nu4 *>(lam);
-        for (uint32_t c0 = threadIdx.x; c0 < nchunk; c0 += 4 * blockDim.x) {
-            nu4 bp[4], bl[4];
+        for (uint32_t c0 = threadIdx.x; c0 < nchunk; c0 += DEPTH * blockDim.x) {
+            nu4 bp[DEPTH], bl[DEPTH];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < DEPTH; ++u) {
                 const uint32_t c = c0 + u * blockDim.x;
                 if (c < nchunk) {
                     const uint64_t x = addr(c << S) >> S;
@@ -289,7 +345,7 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < DEPTH; ++u) {
                 const uint32_t c = c0 + u * blockDim.x;
                 if (c < nchunk) {
                     t16p[bswz(c)] = bp[u];
@@ -305,15 +361,15 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
         }
     }
     __syncthreads();
-    const R *mats = reinterpret_cast<const R *>(d.mats);
+    CPtr<R> mats = cptr(reinterpret_cast<const R *>(d.mats));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int nred = 0;
     // sweeps: each thread loads 8-amplitude groups over the sweep's three
     // tile bits once, applies the sweep's gates in registers in order (taking
     // each inner product right before its gate), and writes the group back
-    const uint32_t groups = 1u << (rec.tb - 3);
-    for (uint32_t sw = rec.sw0; sw < rec.sw1; ++sw) {
-        const SegSweep SW = d.sweeps[sw];
+    const uint32_t groups = 1u << (rec->tb - 3);
+    for (uint32_t sw = rec->sw0; sw < rec->sw1; ++sw) {
+        const SegSweep SW = load_sweep(cptr(d.sweeps) + sw);
         uint32_t off[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j)
@@ -335,7 +391,7 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
             }
             int p = SW.p0;
             for (uint32_t gi = SW.g0; gi < SW.g1; ++gi) {
-                const SegGate G = d.segs[gi];
+                const SegGate G = load_gate(cptr(d.segs) + gi);
                 if (adj && G.slot >= 0) {
                     double re = 0.0, im = 0.0;
                     if (act) reg_inner(l, x, G.xl, G.zl, &re, &im);
@@ -348,7 +404,7 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
                     ++p;
                 }
                 if (act) {
-                    const R *m = mats + 2 * G.mat;
+                    CPtr<R> m = mats + 2 * G.mat;
                     reg_apply(G, x, m);
                     if (adj) reg_apply(G, l, m);
                 }
@@ -364,12 +420,12 @@ __device__ void seg_item(const BatchDev &d, const BatchRec &rec, const BatchInst
         }
         __syncthreads();
     }
-    for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) nred += (adj && d.segs[sg].slot >= 0);
+    for (uint32_t sg = rec->sg0; sg < rec->sg1; ++sg) nred += (adj && cptr(d.segs)[sg].slot >= 0);
     // one partial per inner product: its four waves in a fixed order
     if (adj && nred) {
         int idx = 0;
-        for (uint32_t sg = rec.sg0; sg < rec.sg1; ++sg) {
-            const int slot = d.segs[sg].slot;
+        for (uint32_t sg = rec->sg0; sg < rec->sg1; ++sg) {
+            const int slot = cptr(d.segs)[sg].slot;
             if (slot < 0) continue;
             if ((int)threadIdx.x == (idx & 255)) {
                 double sre = 0.0, sim = 0.0;
@@ -409,8 +465,8 @@ __device__ void hpsi_range(const BatchInst &in, const PauliSumGroup *tg, const P
     using V = typename BAmp<R>::T;
     const V *psi = reinterpret_cast<const V *>(in.psi);
     V *lam = reinterpret_cast<V *>(in.lam);
-    const PauliSumGroup *groups = tg + in.tg_off;
-    const PauliSumTerm *terms = tt + in.tt_off;
+    CPtr<PauliSumGroup> groups = cptr(tg) + in.tg_off;
+    CPtr<PauliSumTerm> terms = cptr(tt) + in.tt_off;
     double sre = 0.0, sim = 0.0;
     for (uint64_t y = y0 + threadIdx.x; y < y1; y += blockDim.x) {
         double ar = 0.0, ai = 0.0;
@@ -442,31 +498,37 @@ __device__ void hpsi_range(const BatchInst &in, const PauliSumGroup *tg, const P
 
 // One work item: item w of record rec.
 template <typename R>
-__device__ void run_item(const BatchDev &d, const BatchRec &rec, uint32_t w, double *red) {
+__device__ void run_item(const BatchDev &d, CPtr<BatchRec> rec, uint32_t w, double *red) {
     using V = typename BAmp<R>::T;
-    const BatchInst in = d.insts[rec.inst];
-    if (rec.kind != BK_HPSI) {
+    const BatchInst in = load_inst(cptr(d.insts) + rec->inst);
+    if (rec->kind != BK_HPSI) {
         seg_item<R>(d, rec, in, w, red, reinterpret_cast<V *>(batch_lds));
         return;
     }
     double re = 0.0, im = 0.0;
     {
-        const uint64_t N = 1ull << in.n, per = N / rec.wgs;
+        const uint64_t N = 1ull << in.n, per = N / rec->wgs;
         hpsi_range<R>(in, d.tg, d.tt, per * w, per * (w + 1), &re, &im);
     }
-    if (rec.slot >= 0) {
+    if (rec->slot >= 0) {
         const double sre = block_sum(re, red);
         const double sim = block_sum(im, red);
         if (threadIdx.x == 0) {
-            double *p = d.partials + in.part_off + 2 * ((uint64_t)rec.slot * in.wgs + w);
+            double *p = d.partials + in.part_off + 2 * ((uint64_t)rec->slot * in.wgs + w);
             p[0] = sre;
             p[1] = sim;
         }
     }
 }
 
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Largest r in [lo, hi) with recs[r].item0 <= x.
-__device__ __forceinline__ uint64_t find_rec(const BatchRec *recs, uint64_t lo, uint64_t hi, uint64_t x) {
+__device__ __forceinline__ uint64_t find_rec(CPtr<BatchRec> recs, uint64_t lo, uint64_t hi, uint64_t x) {
     while (hi - lo > 1) {
         const uint64_t mid = (lo + hi) / 2;
         if (recs[mid].item0 <= x) lo = mid;
@@ -478,9 +540,9 @@ __device__ __forceinline__ uint64_t find_rec(const BatchRec *recs, uint64_t lo, 
 template <typename R>
 __global__ void __launch_bounds__(256) k_batch_step(BatchDev d, int s) {
     __shared__ double red[4];
-    const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], blockIdx.x);
-    const BatchRec &rec = d.recs[r];   // by reference: its qhi[] is indexed at run time
-    run_item<R>(d, rec, blockIdx.x - rec.item0, red);
+    const uint64_t r = find_rec(cptr(d.recs), cptr(d.step_rec)[s], cptr(d.step_rec)[s + 1], blockIdx.x);
+    CPtr<BatchRec> rec = cptr(d.recs) + r;   // by pointer: its qhi[] is indexed at run time
+    run_item<R>(d, rec, blockIdx.x - rec->item0, red);
 }
 
 // counters[0]: next item; counters[1]: error flag; counters[2 + i]: items
@@ -504,23 +566,25 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
             stop_sh = __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         }
         __syncthreads();
-        const uint64_t base = base_sh;
-        if (base >= total || stop_sh) break;
+        // values read from LDS are not known to be uniform; read through
+        // readfirstlane they are, so everything derived stays scalar
+        const uint64_t base = uniform64(base_sh);
+        if (base >= total || __builtin_amdgcn_readfirstlane(stop_sh)) break;
         const uint64_t end = base + chunk < total ? base + chunk : total;
         for (uint64_t item = base; item < end; ++item) {
             uint64_t lo = 0, hi = (uint64_t)d.nsteps;
             while (hi - lo > 1) {
                 const uint64_t mid = (lo + hi) / 2;
-                if (d.step_item[mid] <= item) lo = mid;
+                if (cptr(d.step_item)[mid] <= item) lo = mid;
                 else hi = mid;
             }
             const int s = (int)lo;
-            const uint64_t x = item - d.step_item[s];
-            const uint64_t r = find_rec(d.recs, d.step_rec[s], d.step_rec[s + 1], x);
-            const BatchRec &rec = d.recs[r];   // by reference: its qhi[] is indexed at run time
+            const uint64_t x = item - cptr(d.step_item)[s];
+            const uint64_t r = find_rec(cptr(d.recs), cptr(d.step_rec)[s], cptr(d.step_rec)[s + 1], x);
+            CPtr<BatchRec> rec = cptr(d.recs) + r;   // by pointer: its qhi[] is indexed at run time
             if (threadIdx.x == 0) {
-                unsigned long long *done = &counters[2 + rec.inst];
-                if (pend && pend_inst != rec.inst) {
+                unsigned long long *done = &counters[2 + rec->inst];
+                if (pend && pend_inst != rec->inst) {
                     __hip_atomic_fetch_add(&counters[2 + pend_inst], pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     pend = 0;
                 }
@@ -528,14 +592,14 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
                 // caches under every other workgroup), then acquire once.  A
                 // spin limit of 0 fails every item that has a dependency at all,
                 // so the error path can be forced from the host.
-                const bool force = spin_limit == 0 && rec.need != 0;
-                if (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + pend < rec.need) {
+                const bool force = spin_limit == 0 && rec->need != 0;
+                if (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + pend < rec->need) {
                     if (pend) {
                         __hip_atomic_fetch_add(done, pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         pend = 0;
                     }
                     uint32_t spins = 0;
-                    while (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < rec.need) {
+                    while (force || __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < rec->need) {
                         if (++spins > spin_limit ||
                             __hip_atomic_load(&counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             atomicExch(&counters[1], 1ull);
@@ -548,13 +612,13 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            if (stop_sh) break;
-            run_item<R>(d, rec, (uint32_t)(x - rec.item0), red);
+            if (__builtin_amdgcn_readfirstlane(stop_sh)) break;
+            run_item<R>(d, rec, (uint32_t)(x - rec->item0), red);
             // the barrier makes every wave's stores visible to the workgroup;
             // thread 0's agent-scope release later publishes them device-wide
             __syncthreads();
             if (threadIdx.x == 0) {
-                pend_inst = rec.inst;
+                pend_inst = rec->inst;
                 ++pend;
             }
         }
@@ -563,7 +627,7 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
             pend = 0;
         }
         __syncthreads();
-        if (stop_sh) break;
+        if (__builtin_amdgcn_readfirstlane(stop_sh)) break;
     }
 }
 

@@ -32,6 +32,7 @@ struct DiagRunArgs {
     int kh;                  // selecting bits
     int rest_bits;
     int pattern_major;
+    int spread;
     uint32_t npat;
     uint32_t patoff[64];     // tile-index bits of each active pattern
     int ntab;
@@ -71,23 +72,28 @@ __device__ __forceinline__ V run_cmul(const V &a, const V &b) {
     return r;
 }
 
-// Tables in LDS at entry offsets g * 256 (each table <= 256 entries), so a
-// per-lane index part that includes the offset can be OR-ed with a uniform
-// part below 2^tk.
-template <typename R, int U, int G>
+// Tables at entry offsets g * 256 (each table <= 256 entries), so a per-lane
+// index part that includes the offset can be OR-ed with a uniform part below
+// 2^tk.  LDS_TAB: the tables are staged in LDS once per workgroup; otherwise
+// they are read from global memory, where the few KiB they take stay in the
+// L1 cache, and a workgroup needs no set-up (so it can take a single tile).
+template <typename R, int U, int G, bool LDS_TAB>
 __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R *__restrict__ tables,
                                                   DiagRunArgs a) {
     using V = typename RunAmp<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;   // log2(amplitudes per 16-byte chunk)
     constexpr int A = 1 << S;
-    __shared__ V tab[G * 256];
-    for (int j = threadIdx.x; j < G * 256; j += 256) {
-        V t;
-        t.x = tables[2 * j];
-        t.y = tables[2 * j + 1];
-        tab[j] = t;
+    __shared__ V tab_lds[LDS_TAB ? G * 256 : 1];
+    const V *tab = LDS_TAB ? tab_lds : reinterpret_cast<const V *>(tables);
+    if (LDS_TAB) {
+        for (int j = threadIdx.x; j < G * 256; j += 256) {
+            V t;
+            t.x = tables[2 * j];
+            t.y = tables[2 * j + 1];
+            tab_lds[j] = t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     run_u4 *p16 = reinterpret_cast<run_u4 *>(psi_r);
     const int line0 = (int)(threadIdx.x & 56);   // first lane of this lane's 128-byte line
     auto jof = [&](int g, uint64_t x) {
@@ -104,7 +110,7 @@ __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R
 #pragma unroll
         for (int h = 0; h < A; ++h) jl[g][h] = ((uint32_t)g << 8) | jof(g, ((uint64_t)threadIdx.x << S) | (uint64_t)h);
     constexpr uint64_t per = 256ull * U;
-    const bool spread = (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
+    const bool spread = a.spread && (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
     for (uint64_t it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const uint32_t t = (uint32_t)(spread ? run_xcd_spread(it) : it);   // ntiles <= 2^26
         uint32_t rest, pat;
@@ -184,24 +190,28 @@ __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R
     }
 }
 
-template <typename R, int U>
+template <typename R, int U, bool L>
 hipError_t launch_run_u(int G, R *psi, const R *tabs, const DiagRunArgs &a, int grid, hipStream_t s) {
     switch (G) {
-        case 1: hipLaunchKernelGGL((k_diag_run<R, U, 1>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
-        case 2: hipLaunchKernelGGL((k_diag_run<R, U, 2>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
-        case 3: hipLaunchKernelGGL((k_diag_run<R, U, 3>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
-        case 4: hipLaunchKernelGGL((k_diag_run<R, U, 4>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
+        case 1: hipLaunchKernelGGL((k_diag_run<R, U, 1, L>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
+        case 2: hipLaunchKernelGGL((k_diag_run<R, U, 2, L>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
+        case 3: hipLaunchKernelGGL((k_diag_run<R, U, 3, L>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
+        case 4: hipLaunchKernelGGL((k_diag_run<R, U, 4, L>), dim3(grid), dim3(256), 0, s, psi, tabs, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_run(int U, int G, R *psi, const R *tabs, const DiagRunArgs &a, int grid, hipStream_t s) {
-    switch (U) {
-        case 1: return launch_run_u<R, 1>(G, psi, tabs, a, grid, s);
-        case 2: return launch_run_u<R, 2>(G, psi, tabs, a, grid, s);
-        case 4: return launch_run_u<R, 4>(G, psi, tabs, a, grid, s);
+hipError_t launch_run(int U, bool lds, int G, R *psi, const R *tabs, const DiagRunArgs &a, int grid,
+                      hipStream_t s) {
+    switch (U * 2 + (lds ? 1 : 0)) {
+        case 2: return launch_run_u<R, 1, false>(G, psi, tabs, a, grid, s);
+        case 3: return launch_run_u<R, 1, true>(G, psi, tabs, a, grid, s);
+        case 4: return launch_run_u<R, 2, false>(G, psi, tabs, a, grid, s);
+        case 5: return launch_run_u<R, 2, true>(G, psi, tabs, a, grid, s);
+        case 8: return launch_run_u<R, 4, false>(G, psi, tabs, a, grid, s);
+        case 9: return launch_run_u<R, 4, true>(G, psi, tabs, a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -331,7 +341,7 @@ double active_amplitudes(const std::vector<PhaseTable> &tabs, int n) {
 // above tb (those in the most tables, then the highest) select tiles, and
 // only patterns of them under which some table has an active entry are
 // visited.
-void select_tiles(const SchedPass &p, int n, int tb, int pattern_major, DiagRunArgs *a) {
+void select_tiles(const SchedPass &p, int n, int tb, int pattern_major, cast_dtype dt, DiagRunArgs *a) {
     std::vector<int> cnt(64, 0);
     for (auto &t : p.tabs)
         for (int i = 0; i < t.k; ++i)
@@ -367,6 +377,7 @@ void select_tiles(const SchedPass &p, int n, int tb, int pattern_major, DiagRunA
     for (int s = 0; s < kh; ++s) a->hlowmask[s] = (1ull << (cand[s] - tb)) - 1;
     a->rest_bits = (n - tb) - kh;
     a->pattern_major = pattern_major;
+    a->spread = tuning().diag_spread[dt];
     uint32_t npat = 0;
     for (uint32_t ph = 0; ph < (1u << kh); ++ph) {
         if (!act[ph]) continue;
@@ -517,17 +528,18 @@ cast_status launch_diag_run(void *psi, int n, cast_dtype dt, const SchedPass &p,
         const int S = dt == CAST_C128 ? 0 : 1;
         int tb = S;
         while ((1ull << (tb - S)) < per) ++tb;
-        select_tiles(p, n, tb, tu.diag_order[dt], &a);
+        select_tiles(p, n, tb, tu.diag_order[dt], dt, &a);
         grid = a.ntiles;
         if (grid == 0) return CAST_OK;   // every combined phase is 1
     }
     if (grid > (uint64_t)tu.diag_run_grid[dt]) grid = tu.diag_run_grid[dt];
     const size_t off = p.tab_off * 2;
     hipError_t e;
+    const bool lds = tu.diag_run_lds[dt] != 0;
     if (dt == CAST_C128)
-        e = launch_run<double>(U, a.ntab, (double *)psi, (const double *)dtabs + off, a, (int)grid, stream);
+        e = launch_run<double>(U, lds, a.ntab, (double *)psi, (const double *)dtabs + off, a, (int)grid, stream);
     else
-        e = launch_run<float>(U, a.ntab, (float *)psi, (const float *)dtabs + off, a, (int)grid, stream);
+        e = launch_run<float>(U, lds, a.ntab, (float *)psi, (const float *)dtabs + off, a, (int)grid, stream);
     if (e != hipSuccess) return fail(CAST_EHIP, std::string("diagonal run launch: ") + hipGetErrorString(e));
     return CAST_OK;
 }

@@ -90,8 +90,11 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     // fused gate), qubits per table, chunks per thread, workgroup cap
     int diag_run_tables[3] = {0, 4, 3};
     int diag_run_qubits[3] = {0, 8, 8};
-    int diag_run_unroll[3] = {0, 2, 2};
-    int diag_run_grid[3] = {0, 4096, 4096};
+    int diag_run_unroll[3] = {0, 2, 4};
+    int diag_run_grid[3] = {0, 1 << 16, 1 << 16};
+    int diag_run_lds[3] = {0, 1, 1};     // diagonal runs: phase tables in LDS (1) or read through L1 (0)
+    int mfma_prefetch[3] = {0, 1, 1};    // matrix-core direct kernel: all of a unit's loads before its products
+    int diag_spread[3] = {0, 1, 1};      // diagonal kernels: tiles dealt to XCDs by a digit hash (else round-robin)
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).

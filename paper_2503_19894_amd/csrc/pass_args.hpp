@@ -41,6 +41,7 @@ struct DiagArgs {
     int kh;                 // selecting targets
     int rest_bits;
     int pattern_major;
+    int spread;             // tile number -> XCD by the XOR of its 3-bit digits (else round-robin)
     uint32_t npat;          // active patterns
     uint32_t patoff[64];    // tile-index bits of each active pattern
 };

@@ -36,18 +36,22 @@ def test_dense_haar_22_vs_oracle(dtype, tol):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
 @pytest.mark.parametrize("m3_min_d", [4, 7], ids=["3m_from_d4", "4m_only"])
-def test_dense_mfma_product_forms(dtype, tol, m3_min_d):
+@pytest.mark.parametrize("prefetch", [0, 1], ids=["stepwise_loads", "prefetch"])
+def test_dense_mfma_product_forms(dtype, tol, m3_min_d, prefetch):
     """The matrix-core passes with the three-multiplication complex product
     at every block size (d >= 4) and with the four-product form only, on
     direct and LDS-tile placements (the 4-qubit gate on 0, 2, 5, 9 goes to
-    the tile kernel), against the oracle."""
+    the tile kernel), with the direct kernel's inputs loaded one k-step
+    ahead or all before the first product, against the oracle."""
     n = 16
     gates = dense_haar_layers(n, depth=2, seed=3)
     gates.append(Gate("unitary", (0, 2, 5, 9), matrix=_haar(16, 5)))
     psi0 = random_state(n, seed=2, workload=3)
     want = oracle.run_circuit(n, gates, psi0)
     old = cast.get_tuning("mfma_3m_min_d", dtype)
+    old_pre = cast.get_tuning("mfma_prefetch", dtype)
     cast.set_tuning("mfma_3m_min_d", m3_min_d, dtype)
+    cast.set_tuning("mfma_prefetch", prefetch, dtype)
     try:
         sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
         fc = cast.FusedCircuit(n, gates, k_max=6)
@@ -57,7 +61,8 @@ def test_dense_mfma_product_forms(dtype, tol, m3_min_d):
         err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
     finally:
         cast.set_tuning("mfma_3m_min_d", old, dtype)
-    print(f"dense16 {dtype} 3M from d={m3_min_d}: kernels {sorted(kinds)} err {err:.2e}", flush=True)
+        cast.set_tuning("mfma_prefetch", old_pre, dtype)
+    print(f"dense16 {dtype} 3M from d={m3_min_d} prefetch {prefetch}: kernels {sorted(kinds)} err {err:.2e}", flush=True)
     assert err <= tol
 
 
