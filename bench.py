@@ -795,6 +795,29 @@ def summarize_traffic(fetch_csv, write_csv, command_fetch, command_write):
     return "\n".join(out)
 
 
+def summarize_counters(counter_csv, command, kernel_filter=None):
+    """Per-kernel averages of every PMC counter in a rocprofv3 --pmc CSV
+    (one column per counter), headed by the command and the source digests."""
+    import csv
+    import collections
+
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(counter_csv)):
+        name = r["Kernel_Name"]
+        if kernel_filter and kernel_filter not in name:
+            continue
+        per[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    counters = sorted({c for v in per.values() for c in v})
+    out = ["# rocprofv3 PMC counters, average per dispatch", f"# command: {command}", digest_header(),
+           "# columns: kernel | dispatches | " + " | ".join(counters)]
+    for name, v in sorted(per.items(), key=lambda kv: -len(next(iter(kv[1].values())))):
+        label = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void cast::", "")
+        n = max(len(x) for x in v.values())
+        out.append(f"{label} | {n} | " + " | ".join(f"{sum(v[c]) / len(v[c]):.1f}" if v.get(c) else "-"
+                                                   for c in counters))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -820,6 +843,7 @@ def main():
     ap.add_argument("--families", action="store_true",
                     help="only the circuit-family table (fusion none / size-only / adaptive, per pass and "
                          "cache-blocked); prints one JSON object")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_CSV COMMAND [KERNEL_FILTER]")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"))
     ap.add_argument("--sweep", action="store_true",
                     help="only the single-pass sweep (k = 1..6 x six gate kinds x three placements, 28 and 30 "
@@ -835,6 +859,9 @@ def main():
     if args.summarize_kernel_trace:
         print(summarize_kernel_trace(*args.summarize_kernel_trace))
         return
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters))
+        return
     if args.summarize_traffic:
         print(summarize_traffic(*args.summarize_traffic))
         return
@@ -847,6 +874,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        # one device copy of exactly 1 GiB: the reference the HBM byte
+        # counters of the profiled kernels are scaled by
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.tfim_only:
         print(json.dumps(run_tfim(oracle_check=False)), flush=True)
         return
@@ -868,13 +904,6 @@ def main():
     if args.sweep:
         print(json.dumps({"sweep": run_sweep()}), flush=True)
         return
-    if args.calibrate_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 

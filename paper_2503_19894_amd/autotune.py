@@ -46,6 +46,8 @@ KNOB_CHOICES = [
     ("diag_run_grid", [1 << 12, 1 << 16, 1 << 20]),
     ("diag_run_lds", [0, 1]),
     ("mfma_prefetch", [0, 1]),
+    ("diag_run_reuse", [0, 2, 4, 6]),
+    ("direct_rot", [0, 1, 2, 3]),
 ]
 
 
@@ -134,6 +136,24 @@ def _timed_passes(sv, fc, reps=3):
     return np.min([sv.apply_circuit_timed(fc) for _ in range(reps)], axis=0)
 
 
+def stream_rate(buf, nbytes, reps=5):
+    """Read + write GB/s of the library's streaming kernel over `buf`
+    (in-place scale by 1), best of reps."""
+    import ctypes
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    run = lambda: cast.stream_scale(ctypes.c_void_p(buf.data_ptr()), nbytes, 1.0, 1, 0, stream)  # noqa: E731
+    run()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def path_costs(n, dtype, log):
     """Rates the path planner prices plans with (measured on 2^n states):
     algorithmic GB/s of each pass kernel, the matrix cores' GFLOP/s by block
@@ -199,9 +219,12 @@ def path_costs(n, dtype, log):
     for d, (per_gate, _) in seg.items():
         out[f"seg_gate{d}"] = per_gate
     base = [a for _, a in seg.values() if a > 0]
+    S = (1 << n) * (16 if dtype == torch.complex128 else 8)
+    stream = stream_rate(psi, S)
     if base:
-        S = (1 << n) * (16 if dtype == torch.complex128 else 8)
-        out["seg_bw"] = 2.0 * S / (max(float(np.median(base)) - out["launch_ms"], 1e-3) * 1e-3) / 1e9
+        # a segment's state read and write cannot beat the streaming kernel
+        fit = 2.0 * S / (max(float(np.median(base)) - out["launch_ms"], 1e-3) * 1e-3) / 1e9
+        out["seg_bw"] = min(fit, stream)
     del sv, psi, small
     torch.cuda.empty_cache()
     log("  " + ", ".join(f"{k}={v:.4g}" for k, v in sorted(out.items())))

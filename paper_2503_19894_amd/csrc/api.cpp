@@ -526,6 +526,10 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "diag_run_lds") { *hi = 1; return &t.diag_run_lds[i]; }
     if (key == "mfma_prefetch") { *hi = 1; return &t.mfma_prefetch[i]; }
     if (key == "diag_spread") { *hi = 1; return &t.diag_spread[i]; }
+    if (key == "diag_run_reuse") { *hi = 12; return &t.diag_run_reuse[i]; }
+    if (key == "direct_rot") { *hi = 16; return &t.direct_rot[i]; }
+    if (key == "direct_rot_lo") { *hi = 34; return &t.direct_rot_lo[i]; }
+    if (key == "direct_rot_hi") { *hi = 34; return &t.direct_rot_hi[i]; }
     return nullptr;
 }
 

@@ -116,7 +116,12 @@ __global__ void __launch_bounds__(256) k_direct(R *__restrict__ psi_r, const R *
     const uint64_t items = a.ngroups * a.nblk;
     constexpr uint64_t per_iter = 256ull * IPT;
     const uint64_t nfull = items / per_iter;
-    for (uint64_t it = blockIdx.x; it < nfull; it += gridDim.x) {
+    for (uint64_t it0 = blockIdx.x; it0 < nfull; it0 += gridDim.x) {
+        // iteration order: rotating the iteration index spreads the
+        // workgroups in flight over more DRAM rows of each of the gate's
+        // 2^d planes (nfull is then a power of two, 2^it_bits)
+        const uint64_t it =
+            a.rot ? (((it0 << a.rot) | (it0 >> (a.it_bits - a.rot))) & ((1ull << a.it_bits) - 1)) : it0;
         uint64_t base[IPT];
         const R *m[IPT];
         V v[IPT][N];
@@ -702,13 +707,27 @@ static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const 
     if (grid > (uint64_t)tuning().max_grid[dt]) grid = tuning().max_grid[dt];
     if (grid < 1) grid = 1;
     const int g = (int)grid;
+    PassArgs b = a;
+    b.rot = b.it_bits = 0;
+    {
+        // rotated iteration order for passes whose lowest target lies in
+        // [direct_rot_lo, direct_rot_hi] (needs a power-of-two iteration count)
+        const Tuning &tu = tuning();
+        const uint64_t nfull = items / (256ull * ipt);
+        const int q0 = __builtin_ctzll(a.lowmask[0] + 1);   // lowest target
+        if (tu.direct_rot[dt] > 0 && nfull > 1 && !(nfull & (nfull - 1)) && q0 >= tu.direct_rot_lo[dt] &&
+            q0 <= tu.direct_rot_hi[dt]) {
+            b.it_bits = __builtin_ctzll(nfull);
+            b.rot = tu.direct_rot[dt] < b.it_bits ? tu.direct_rot[dt] : 0;
+        }
+    }
     switch (ipt * 2 + (nt ? 1 : 0)) {
-        case 2: launch_direct_t<R, 1, false>(D, psi, m, a, g, s); break;
-        case 3: launch_direct_t<R, 1, true>(D, psi, m, a, g, s); break;
-        case 4: launch_direct_t<R, 2, false>(D, psi, m, a, g, s); break;
-        case 5: launch_direct_t<R, 2, true>(D, psi, m, a, g, s); break;
-        case 8: launch_direct_t<R, 4, false>(D, psi, m, a, g, s); break;
-        case 9: launch_direct_t<R, 4, true>(D, psi, m, a, g, s); break;
+        case 2: launch_direct_t<R, 1, false>(D, psi, m, b, g, s); break;
+        case 3: launch_direct_t<R, 1, true>(D, psi, m, b, g, s); break;
+        case 4: launch_direct_t<R, 2, false>(D, psi, m, b, g, s); break;
+        case 5: launch_direct_t<R, 2, true>(D, psi, m, b, g, s); break;
+        case 8: launch_direct_t<R, 4, false>(D, psi, m, b, g, s); break;
+        case 9: launch_direct_t<R, 4, true>(D, psi, m, b, g, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

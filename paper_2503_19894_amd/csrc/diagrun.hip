@@ -38,6 +38,7 @@ struct DiagRunArgs {
     int ntab;
     int tk[kRunMaxTables];   // qubits of table g
     int tq[kRunMaxTables][kRunMaxQ];
+    uint64_t amask[kRunMaxTables][4];   // bit j of table g: entry j differs from 1
 };
 
 namespace {
@@ -62,6 +63,12 @@ __device__ __forceinline__ uint64_t run_xcd_spread(uint64_t it) {
     uint64_t f = 0;
     for (uint64_t y = r; y; y >>= 3) f ^= y;
     return (r << 3) | ((it ^ f) & 7);
+}
+
+// Bit j (< 256) of a table's activity mask (four words, kernel arguments).
+__device__ __forceinline__ bool run_active(const uint64_t *m, uint32_t j) {
+    const uint64_t w = (j & 128u) ? ((j & 64u) ? m[3] : m[2]) : ((j & 64u) ? m[1] : m[0]);
+    return (w >> (j & 63u)) & 1ull;
 }
 
 template <typename V>
@@ -111,7 +118,18 @@ __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R
         for (int h = 0; h < A; ++h) jl[g][h] = ((uint32_t)g << 8) | jof(g, ((uint64_t)threadIdx.x << S) | (uint64_t)h);
     constexpr uint64_t per = 256ull * U;
     const bool spread = a.spread && (a.ntiles & 7) == 0 && (gridDim.x & 7) == 0;
-    for (uint64_t it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
+    // Two tiles in flight per workgroup: the loads of the next tile are
+    // issued before the current one's table lookups and multiplies, so the
+    // lookups (G per amplitude) overlap memory latency instead of adding to
+    // it.  A tile's loads depend only on the activity masks (no memory).
+    struct Stage {
+        run_u4 w[U];
+        bool act[U];
+        uint32_t hact[U];
+        uint32_t ju[U][G];
+        uint64_t tile;
+    };
+    auto issue = [&](uint64_t it, Stage &st) {
         const uint32_t t = (uint32_t)(spread ? run_xcd_spread(it) : it);   // ntiles <= 2^26
         uint32_t rest, pat;
         if (a.pattern_major) {
@@ -121,43 +139,69 @@ __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R
             rest = t / a.npat;
             pat = t - rest * a.npat;
         }
-        const uint64_t tile = run_deposit(rest, a.hlowmask, a.kh) | a.patoff[pat];
-        run_u4 w[U];
-        V ph[U][A];
-        bool act[U];
-        uint32_t hact[U];
+        st.tile = run_deposit(rest, a.hlowmask, a.kh) | a.patoff[pat];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t c0 = tile * per + (uint64_t)u * 256;   // uniform
-            uint32_t ju[G];
+            const uint64_t c0 = st.tile * per + (uint64_t)u * 256;   // uniform
 #pragma unroll
-            for (int g = 0; g < G; ++g) ju[g] = jof(g, c0 << S);
+            for (int g = 0; g < G; ++g) st.ju[u][g] = jof(g, c0 << S);
             uint32_t m = 0;
 #pragma unroll
             for (int h = 0; h < A; ++h) {
-                V p = tab[jl[0][h] | ju[0]];
-                bool on = p.x != (R)1 || p.y != (R)0;
+                bool on = false;
 #pragma unroll
-                for (int g = 1; g < G; ++g) {
-                    const V e = tab[jl[g][h] | ju[g]];
-                    on |= e.x != (R)1 || e.y != (R)0;
-                    p = run_cmul(p, e);
-                }
-                ph[u][h] = p;
+                for (int g = 0; g < G; ++g) on |= run_active(a.amask[g], (jl[g][h] & 255u) | st.ju[u][g]);
                 m |= (uint32_t)on << h;
             }
-            hact[u] = m;
-            act[u] = ((__ballot(m != 0) >> line0) & 0xffull) != 0;
-            if (act[u]) w[u] = __builtin_nontemporal_load(p16 + c0 + threadIdx.x);
+            st.hact[u] = m;
+            st.act[u] = ((__ballot(m != 0) >> line0) & 0xffull) != 0;
+            if (st.act[u]) st.w[u] = __builtin_nontemporal_load(p16 + c0 + threadIdx.x);
         }
+    };
+    // Every amplitude of an active line is multiplied by its phase product:
+    // where all entries are 1 the product is exactly 1 and so is the
+    // multiply, which saves a divergent branch per amplitude.  With two
+    // amplitudes per chunk (complex64) a table without qubit 0 gives both
+    // the same entry, read once.
+    auto finish = [&](Stage &st) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!act[u]) continue;
-            V *v = reinterpret_cast<V *>(&w[u]);
+            if (!st.act[u]) continue;
+            V *v = reinterpret_cast<V *>(&st.w[u]);
+            V p[A];
 #pragma unroll
-            for (int h = 0; h < A; ++h)
-                if ((hact[u] >> h) & 1u) v[h] = run_cmul(v[h], ph[u][h]);
-            __builtin_nontemporal_store(w[u], p16 + tile * per + (uint64_t)u * 256 + threadIdx.x);
+            for (int g = 0; g < G; ++g) {
+                V e[A];
+                e[0] = tab[jl[g][0] | st.ju[u][g]];
+#pragma unroll
+                for (int h = 1; h < A; ++h) {
+                    if (a.tq[g][0] != 0) e[h] = e[0];
+                    else e[h] = tab[jl[g][h] | st.ju[u][g]];
+                }
+#pragma unroll
+                for (int h = 0; h < A; ++h) p[h] = g ? run_cmul(p[h], e[h]) : e[h];
+            }
+#pragma unroll
+            for (int h = 0; h < A; ++h) v[h] = run_cmul(v[h], p[h]);
+            __builtin_nontemporal_store(st.w[u], p16 + st.tile * per + (uint64_t)u * 256 + threadIdx.x);
+        }
+    };
+    uint64_t it = blockIdx.x;
+    if (it < a.ntiles) {
+        Stage s0, s1;
+        issue(it, s0);
+        for (;;) {
+            const uint64_t i1 = it + gridDim.x;
+            const bool more1 = i1 < a.ntiles;   // uniform
+            if (more1) issue(i1, s1);
+            finish(s0);
+            if (!more1) break;
+            const uint64_t i2 = i1 + gridDim.x;
+            const bool more2 = i2 < a.ntiles;
+            if (more2) issue(i2, s0);
+            finish(s1);
+            if (!more2) break;
+            it = i2;
         }
     }
     // a state smaller than one tile: one chunk per lane (8-lane groups are
@@ -187,6 +231,127 @@ __global__ void __launch_bounds__(256) k_diag_run(R *__restrict__ psi_r, const R
         for (int h = 0; h < A; ++h)
             if ((m >> h) & 1u) v[h] = run_cmul(v[h], p[h]);
         p16[c] = wv;
+    }
+}
+
+// Phase reuse.  The high amplitude-index bits (above a lane's chunk) split
+// into D, the bits some table depends on, and F, the bits no table touches.
+// Amplitudes that differ only in F bits get the same phase, so a work unit
+// takes one pattern of the D bits and 2^c patterns of the F bits: each lane
+// looks its phase product up once (G table reads) and then streams 2^c
+// chunks, one complex multiply per amplitude.  Line-level skipping is as
+// above (the activity of a line does not depend on F bits either).
+struct DiagReuseArgs {
+    uint64_t nunits;        // D patterns x blocks of 2^c F patterns
+    int nd, nf, c;          // dependent and free high bits; log2 F patterns per unit
+    int dpos[40];           // amplitude-index positions of the D bits (ascending)
+    int fpos[40];           // amplitude-index positions of the F bits (ascending)
+    int ntab;
+    int tk[kRunMaxTables];
+    int tq[kRunMaxTables][kRunMaxQ];
+};
+
+template <typename R, int G, bool LDS_TAB, int UI>
+__global__ void __launch_bounds__(256) k_diag_run_reuse(R *__restrict__ psi_r, const R *__restrict__ tables,
+                                                        DiagReuseArgs a) {
+    using V = typename RunAmp<R>::T;
+    constexpr int S = sizeof(V) == 16 ? 0 : 1;   // log2(amplitudes per 16-byte chunk)
+    constexpr int A = 1 << S;
+    __shared__ V tab_lds[LDS_TAB ? G * 256 : 1];
+    const V *tab = LDS_TAB ? tab_lds : reinterpret_cast<const V *>(tables);
+    if (LDS_TAB) {
+        for (int j = threadIdx.x; j < G * 256; j += 256) {
+            V t;
+            t.x = tables[2 * j];
+            t.y = tables[2 * j + 1];
+            tab_lds[j] = t;
+        }
+        __syncthreads();
+    }
+    run_u4 *p16 = reinterpret_cast<run_u4 *>(psi_r);
+    const int line0 = (int)(threadIdx.x & 56);
+    auto jof = [&](int g, uint64_t x) {
+        uint32_t j = 0;
+        for (int i = 0; i < a.tk[g]; ++i) j |= (uint32_t)((x >> a.tq[g][i]) & 1u) << i;
+        return j;
+    };
+    uint32_t jl[G][A];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int h = 0; h < A; ++h) jl[g][h] = ((uint32_t)g << 8) | jof(g, ((uint64_t)threadIdx.x << S) | (uint64_t)h);
+    const uint32_t nin = 1u << a.c;
+    const int bshift = a.nf - a.c;
+    for (uint64_t unit = blockIdx.x; unit < a.nunits; unit += gridDim.x) {
+        const uint64_t o = unit >> bshift, b = unit & ((1ull << bshift) - 1);
+        uint64_t xo = 0, xb = 0;   // uniform
+        for (int i = 0; i < a.nd; ++i) xo |= ((o >> i) & 1ull) << a.dpos[i];
+        for (int i = a.c; i < a.nf; ++i) xb |= ((b >> (i - a.c)) & 1ull) << a.fpos[i];
+        V p[A];
+        bool on = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t ju = jof(g, xo);
+#pragma unroll
+            for (int h = 0; h < A; ++h) {
+                const V e = tab[jl[g][h] | ju];
+                on |= e.x != (R)1 || e.y != (R)0;
+                p[h] = g ? run_cmul(p[h], e) : e;
+            }
+        }
+        const uint64_t bal = __ballot(on);
+        if (!bal) continue;                                 // no active line in this wave
+        const bool act = ((bal >> line0) & 0xffull) != 0;   // this lane's line
+        const uint64_t cbase = ((xo | xb) >> S) + threadIdx.x;
+        for (uint32_t j0 = 0; j0 < nin; j0 += UI) {
+            run_u4 w[UI];
+            uint64_t ci[UI];
+#pragma unroll
+            for (int u = 0; u < UI; ++u) {
+                const uint32_t j = j0 + u;
+                uint64_t xj = 0;
+                for (int i = 0; i < a.c; ++i) xj |= (uint64_t)((j >> i) & 1u) << a.fpos[i];
+                ci[u] = cbase + (xj >> S);
+                if (j < nin && act) w[u] = __builtin_nontemporal_load(p16 + ci[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < UI; ++u) {
+                if (j0 + u >= nin || !act) continue;
+                V *v = reinterpret_cast<V *>(&w[u]);
+#pragma unroll
+                for (int h = 0; h < A; ++h) v[h] = run_cmul(v[h], p[h]);
+                __builtin_nontemporal_store(w[u], p16 + ci[u]);
+            }
+        }
+    }
+}
+
+template <typename R, int G, int UI>
+hipError_t launch_reuse_g(bool lds, R *psi, const R *tabs, const DiagReuseArgs &a, int grid, hipStream_t s) {
+    if (lds) hipLaunchKernelGGL((k_diag_run_reuse<R, G, true, UI>), dim3(grid), dim3(256), 0, s, psi, tabs, a);
+    else hipLaunchKernelGGL((k_diag_run_reuse<R, G, false, UI>), dim3(grid), dim3(256), 0, s, psi, tabs, a);
+    return hipGetLastError();
+}
+
+template <typename R, int UI>
+hipError_t launch_reuse_u(int G, bool lds, R *psi, const R *tabs, const DiagReuseArgs &a, int grid, hipStream_t s) {
+    switch (G) {
+        case 1: return launch_reuse_g<R, 1, UI>(lds, psi, tabs, a, grid, s);
+        case 2: return launch_reuse_g<R, 2, UI>(lds, psi, tabs, a, grid, s);
+        case 3: return launch_reuse_g<R, 3, UI>(lds, psi, tabs, a, grid, s);
+        case 4: return launch_reuse_g<R, 4, UI>(lds, psi, tabs, a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t launch_reuse(int UI, int G, bool lds, R *psi, const R *tabs, const DiagReuseArgs &a, int grid,
+                        hipStream_t s) {
+    switch (UI) {
+        case 1: return launch_reuse_u<R, 1>(G, lds, psi, tabs, a, grid, s);
+        case 2: return launch_reuse_u<R, 2>(G, lds, psi, tabs, a, grid, s);
+        case 4: return launch_reuse_u<R, 4>(G, lds, psi, tabs, a, grid, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -518,6 +683,37 @@ cast_status launch_diag_run(void *psi, int n, cast_dtype dt, const SchedPass &p,
     for (int g = 0; g < a.ntab; ++g) {
         a.tk[g] = p.tabs[g].k;
         for (int i = 0; i < p.tabs[g].k; ++i) a.tq[g][i] = p.tabs[g].q[i];
+        for (size_t j = 0; j < p.tabs[g].ph.size(); ++j)
+            if (!snapped_one(p.tabs[g].ph[j])) a.amask[g][j >> 6] |= 1ull << (j & 63);
+    }
+    const int Sb = dt == CAST_C128 ? 0 : 1;
+    const int LB = 8 + Sb;   // amplitude-index bits inside one 256-lane tile
+    if (tu.diag_run_reuse[dt] > 0 && n > LB) {
+        DiagReuseArgs r;
+        memset(&r, 0, sizeof r);
+        r.ntab = a.ntab;
+        uint64_t used = 0;
+        for (int g = 0; g < a.ntab; ++g) {
+            r.tk[g] = a.tk[g];
+            for (int i = 0; i < a.tk[g]; ++i) r.tq[g][i] = a.tq[g][i], used |= 1ull << a.tq[g][i];
+        }
+        for (int q = LB; q < n; ++q) {
+            if ((used >> q) & 1ull) r.dpos[r.nd++] = q;
+            else r.fpos[r.nf++] = q;
+        }
+        r.c = std::min(r.nf, tu.diag_run_reuse[dt]);
+        r.nunits = 1ull << (n - LB - r.c);
+        uint64_t grid = std::min<uint64_t>(r.nunits, (uint64_t)tu.diag_run_grid[dt]);
+        const size_t off = p.tab_off * 2;
+        const bool lds = tu.diag_run_lds[dt] != 0;
+        const int UI = tu.diag_run_unroll[dt];
+        hipError_t e;
+        if (dt == CAST_C128)
+            e = launch_reuse<double>(UI, r.ntab, lds, (double *)psi, (const double *)dtabs + off, r, (int)grid, stream);
+        else
+            e = launch_reuse<float>(UI, r.ntab, lds, (float *)psi, (const float *)dtabs + off, r, (int)grid, stream);
+        if (e != hipSuccess) return fail(CAST_EHIP, std::string("diagonal run launch: ") + hipGetErrorString(e));
+        return CAST_OK;
     }
     a.nchunks = ((uint64_t)1 << n) * amp_bytes(dt) / 16;
     if (a.nchunks == 0) a.nchunks = 1;   // c64, n = 1

@@ -95,6 +95,14 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int diag_run_lds[3] = {0, 1, 1};     // diagonal runs: phase tables in LDS (1) or read through L1 (0)
     int mfma_prefetch[3] = {0, 1, 1};    // matrix-core direct kernel: all of a unit's loads before its products
     int diag_spread[3] = {0, 1, 1};      // diagonal kernels: tiles dealt to XCDs by a digit hash (else round-robin)
+    // diagonal runs: log2 of the free-bit patterns one work unit streams with
+    // one phase lookup per lane (phase reuse; 0: the tiled run kernel)
+    int diag_run_reuse[3] = {0, 2, 2};
+    // direct kernel: iteration order rotated left by direct_rot bits (0: in
+    // order) for passes whose lowest target is in [direct_rot_lo, direct_rot_hi]
+    int direct_rot[3] = {0, 0, 0};
+    int direct_rot_lo[3] = {0, 18, 18};
+    int direct_rot_hi[3] = {0, 25, 25};
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).

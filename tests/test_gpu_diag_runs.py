@@ -17,7 +17,7 @@ import paper_2503_19894_amd as cast  # noqa: E402
 from circuits import Gate, iqp, qft, random_state  # noqa: E402
 
 TOL = {torch.complex128: 1e-12, torch.complex64: 1e-5}
-KEYS = ("diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid", "diag_run_lds")
+KEYS = ("diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid", "diag_run_lds", "diag_run_reuse")
 
 
 @pytest.fixture
@@ -74,11 +74,15 @@ def test_runs_vs_oracle(knobs, dtype, circ, n):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64], ids=["c128", "c64"])
-@pytest.mark.parametrize("tables,qubits,unroll,grid,lds", [
-    (1, 8, 1, 256, 1), (2, 4, 2, 4096, 1), (2, 8, 4, 256, 0), (3, 6, 1, 1 << 20, 0), (4, 8, 2, 4096, 0),
-    (4, 5, 4, 1 << 20, 1), (3, 8, 1, 1 << 24, 0), (4, 8, 2, 1 << 24, 1)])
-def test_run_knobs_vs_oracle(knobs, dtype, tables, qubits, unroll, grid, lds):
-    for key, v in zip(KEYS, (tables, qubits, unroll, grid, lds)):
+@pytest.mark.parametrize("tables,qubits,unroll,grid,lds,reuse", [
+    (1, 8, 1, 256, 1, 0), (2, 4, 2, 4096, 1, 0), (2, 8, 4, 256, 0, 0), (3, 6, 1, 1 << 20, 0, 0),
+    (4, 8, 2, 4096, 0, 0), (4, 5, 4, 1 << 20, 1, 0), (3, 8, 1, 1 << 24, 0, 0), (4, 8, 2, 1 << 24, 1, 0),
+    (1, 8, 1, 256, 1, 1), (2, 4, 2, 4096, 0, 2), (3, 8, 4, 1 << 16, 1, 4), (4, 8, 1, 1 << 20, 0, 4),
+    (4, 6, 2, 256, 1, 12), (2, 8, 4, 1 << 24, 0, 12)])
+def test_run_knobs_vs_oracle(knobs, dtype, tables, qubits, unroll, grid, lds, reuse):
+    """Each knob setting against the oracle; reuse = 0 is the tiled run
+    kernel, reuse > 0 the phase-reuse kernel (F patterns per unit)."""
+    for key, v in zip(KEYS, (tables, qubits, unroll, grid, lds, reuse)):
         cast.set_tuning(key, v, dtype)
     runs = 0
     for circ in sorted(CIRCUITS):
@@ -87,7 +91,7 @@ def test_run_knobs_vs_oracle(knobs, dtype, tables, qubits, unroll, grid, lds):
             err, sched, nf = _run(n, gates, dtype, k_max=4)
             runs += sum(p["kernel"] == 6 for p in sched)
             assert max(p["tables"] for p in sched) <= tables
-            print(f"knobs {tables}/{qubits}/{unroll}/{grid}/{lds} {circ} n={n} {dtype}: {len(sched)} passes, "
+            print(f"knobs {tables}/{qubits}/{unroll}/{grid}/{lds}/{reuse} {circ} n={n} {dtype}: {len(sched)} passes, "
                   f"max |d amp| {err:.2e}", flush=True)
             assert err <= TOL[dtype]
     assert runs > 0

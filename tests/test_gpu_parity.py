@@ -167,6 +167,40 @@ def test_direct_block_runs(dtype, chunk_log):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+@pytest.mark.parametrize("rot", [1, 3, 7])
+def test_direct_rotated_order(dtype, rot):
+    """The direct kernel with its iteration order rotated (every target
+    height, so small iteration counts clamp the rotation too): fused QFT and
+    several-block gates against the oracle."""
+    n = 17
+    rng = np.random.default_rng(23)
+    gates = qft(n)
+    for qs, d in (((4, 6, 9, 12, 16), 1), ((5, 7, 8, 15), 2), ((10, 11, 13), 3)):
+        k = len(qs)
+        u = haar_unitary(1 << d, rng)
+        ph = np.exp(1j * rng.uniform(0.1, 6.0, 1 << (k - d)))
+        gates.append(Gate("unitary", qs, matrix=np.kron(np.diag(ph), u)))
+    psi0 = random_state(n, seed=6, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    keys = ("direct_rot", "direct_rot_lo", "direct_rot_hi")
+    old = {key: cast.get_tuning(key, dtype) for key in keys}
+    for key, v in zip(keys, (rot, 0, 34)):
+        cast.set_tuning(key, v, dtype)
+    try:
+        fc = cast.FusedCircuit(n, gates, k_max=4)
+        kinds = [p["kernel"] for p in fc.schedule(dtype)]
+        sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+        sv.apply_circuit(fc)
+        err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    finally:
+        for key, v in old.items():
+            cast.set_tuning(key, v, dtype)
+    note(f"direct rotation {rot} {dtype}: kernels {kinds} err {err:.2e}")
+    assert 0 in kinds
+    assert err <= TOL[dtype]
+
+
 def test_qft_closed_form_via_fft():
     n = 20
     psi0 = random_state(n, seed=3, workload=2)
