@@ -52,7 +52,11 @@ def kernel_label(info, dtype_name):
     r = "double" if dtype_name == "c128" else "float"
     if kind == 6:
         lds = "true" if cast.get_tuning("diag_run_lds", dt) else "false"
-        return f"k_diag_run<{r}, {cast.get_tuning('diag_run_unroll', dt)}, {info['tables']}, {lds}>"
+        u = cast.get_tuning("diag_run_unroll", dt)
+        tile_bits = 8 if dtype_name == "c128" else 9   # amplitude-index bits inside one 256-lane tile
+        if cast.get_tuning("diag_run_reuse", dt) > 0 and info.get("n", 30) > tile_bits:
+            return f"k_diag_run_reuse<{r}, {info['tables']}, {lds}, {u}>"
+        return f"k_diag_run<{r}, {u}, {info['tables']}, {lds}>"
     if kind == 3:
         lds = "true" if cast.get_tuning("diag_lds_table", dt) else "false"
         return f"k_diag<{r}, {cast.get_tuning('diag_unroll', dt)}, {lds}>"
@@ -140,6 +144,7 @@ def schedule_infos(fc, dtype):
     block dimension of its fused gate for single-gate passes."""
     infos = fc.schedule(dtype)
     for inf in infos:
+        inf["n"] = fc.n
         if inf["kernel"] != 6 and inf["kernel"] >= 0:
             inf["d"] = fc.pass_info(inf["first"], dtype)["d"]
     return infos

@@ -201,6 +201,29 @@ def test_direct_rotated_order(dtype, rot):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_tile_idle_runs_skipped(dtype):
+    """LDS-tile passes whose identity blocks are selected by high targets
+    (controlled gates with a low target and high controls, a low-target
+    block chosen by a high qubit): the tile holds runs of identity blocks
+    too, which must come back unchanged; the result matches the oracle."""
+    n = 17
+    rng = np.random.default_rng(31)
+    gates = [gate_sweep("ctrl", 2, (15, 0), seed=1)[0], gate_sweep("ctrl", 3, (12, 16, 1), seed=2)[0],
+             Gate("unitary", (0, 1, 13), matrix=np.kron(np.diag([1.0, np.exp(0.7j)]), haar_unitary(4, rng))),
+             Gate("unitary", (2, 3, 14, 15), matrix=np.kron(np.diag([1, 1, 1, np.exp(0.3j)]), haar_unitary(4, rng)))]
+    psi0 = random_state(n, seed=8, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    fc = cast.FusedCircuit(n, gates, k_max=1)
+    kinds = [fc.pass_info(i, dtype)["kernel"] for i in range(len(fc))]
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+    sv.apply_circuit(fc)
+    err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    note(f"tile idle runs {dtype}: kernels {kinds} err {err:.2e}")
+    assert set(kinds) == {1}
+    assert err <= TOL[dtype]
+
+
 def test_qft_closed_form_via_fft():
     n = 20
     psi0 = random_state(n, seed=3, workload=2)
