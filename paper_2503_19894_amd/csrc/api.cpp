@@ -764,7 +764,9 @@ cast_status circuit_pass_info(const cast_fused *fc, int n, cast_dtype dt, size_t
     const SchedPass &sp = sc->passes[i];
     if (first) *first = sp.first;
     if (count) *count = sp.count;
-    if (kernel) *kernel = sp.kind;
+    // a single gate's kernel follows the current knobs (the cached schedule
+    // only keys on the knobs that change which gates form runs)
+    if (kernel) *kernel = (sp.kind == 6 || sp.kind < 0) ? sp.kind : pass_kernel_kind(n, dt, fc->plans[sp.first]);
     if (tables) *tables = (int)sp.tabs.size();
     if (sp.kind == 6) {
         if (alg_bytes) *alg_bytes = 2.0 * (double)amp_bytes(dt) * sp.active_amps;
