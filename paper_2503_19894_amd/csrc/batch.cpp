@@ -192,10 +192,11 @@ static void free_batch(cast_batch *b) {
     delete b;
 }
 
-// Tile of a segment: 2^11 complex128 or 2^12 complex64 amplitudes (psi and
-// lambda together 64 KiB of LDS); CAST_BATCH_TILE_BITS overrides.
+// Tile of a segment: 2^batch_tile_bits amplitudes (the tuning knob, 11 by
+// default for both dtypes: psi and lambda together 64 KiB of LDS in
+// complex128, 32 KiB in complex64); CAST_BATCH_TILE_BITS overrides.
 static int batch_tile_bits(cast_dtype dt) {
-    int tb = dt == CAST_C128 ? 11 : 12;
+    int tb = tuning().batch_tile_bits[dt == CAST_C64 ? CAST_C64 : CAST_C128];
     if (const char *e = std::getenv("CAST_BATCH_TILE_BITS")) tb = std::min(12, std::max(4, atoi(e)));
     return tb;
 }
@@ -334,8 +335,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
     std::vector<BatchInst> hinst(n_inst);
     size_t state_elems = 0;
     // amplitudes per work item, and the cache budget of an instance group
-    // tile of a segment: 2^11 complex128 or 2^12 complex64 amplitudes, psi
-    // and lambda together 64 KiB of LDS
+    // tile of a segment: 2^batch_tile_bits amplitudes of psi and of lambda
     const int tile_bits = batch_tile_bits(dt);
     // per-step launches: groups sized for the 256 MB last-level cache; the
     // persistent launch keeps every instance in one step-major stream

@@ -103,6 +103,8 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int direct_rot[3] = {0, 0, 0};
     int direct_rot_lo[3] = {0, 18, 18};
     int direct_rot_hi[3] = {0, 25, 25};
+    // batched programs: log2 amplitudes of a segment's LDS tile
+    int batch_tile_bits[3] = {0, 11, 11};
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).

@@ -14,7 +14,7 @@ import oracle
 import paper_2503_19894_amd as cast
 from circuits import hea_vqa, tfim_trotter, random_state, vqa_thetas, tfim_fields
 
-TB = {torch.complex128: 11, torch.complex64: 12}
+TB = {dt: cast.get_tuning("batch_tile_bits", dt) for dt in (torch.complex128, torch.complex64)}
 
 
 def _qubits(g):
