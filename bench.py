@@ -5,7 +5,11 @@ Workload: 30-qubit QFT (30 H + 435 controlled-phase + 15 SWAP gates) applied
 to a random normalised state with i.i.d. complex Gaussian amplitudes, after
 host fusion with k_max = 5.  One step = one application of the whole fused
 circuit (every fused gate = one in-place pass over the 2^30 amplitudes), with
-the state already resident in HBM.
+the state already resident in HBM.  Before the warmup the direct passes'
+launch shapes are measured on the state (circuit_tune, extras.<dtype>.tune),
+which is then drawn again from its seed; marker dispatches bracket the timed
+steps so that kernel traces can be cut to them (--summarize-kernel-trace on a
+per-dispatch trace).
 
 Headline value: effective HBM GB/s per fused-gate pass = the passes'
 algorithmic bytes (every amplitude of a non-identity block read and written
@@ -76,7 +80,24 @@ def kernel_label(info, dtype_name):
     return f"k_tile<{d}, {r}, true, {two}>"
 
 
-def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
+def region_marker():
+    """Queues the marker dispatch that brackets a timed region in kernel
+    traces: the streaming reference kernel on one 16-byte chunk (one
+    workgroup of 256 lanes, a grid no other launch here has)."""
+    import ctypes
+
+    import torch
+
+    import paper_2503_19894_amd as cast
+
+    buf = getattr(region_marker, "buf", None)
+    if buf is None:
+        buf = region_marker.buf = torch.ones(2, dtype=torch.float64, device="cuda")
+    cast.stream_scale(ctypes.c_void_p(buf.data_ptr()), 16, 1.0, 1, 1,
+                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0, tune_reps=3):
     import numpy as np
     import torch
 
@@ -93,15 +114,27 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
     npass = len(infos)
     psi = random_state_torch(n, seed=seed, device="cuda", dtype=dtype)
     sv = cast.StateVector(n, tensor=psi)
+    tune = None
+    if tune_reps > 0:
+        # launch shapes of the direct passes, measured on this state (which
+        # the tuner changes), then the input again
+        t0 = time.perf_counter()
+        before, after = sv.tune_circuit(fc, reps=tune_reps)
+        tune = {"reps": tune_reps, "s": round(time.perf_counter() - t0, 3), "direct_ms_before": round(before, 4),
+                "direct_ms_after": round(after, 4),
+                "shapes": {i: list(fc.pass_shape(dtype, i)) for i, inf in enumerate(infos) if inf["kernel"] == 0}}
+        psi.copy_(random_state_torch(n, seed=seed, device="cuda", dtype=dtype))
     for _ in range(warmup):
         sv.apply_circuit(fc)
     torch.cuda.synchronize()
     per_pass = np.zeros(npass)
+    region_marker()
     t0 = time.perf_counter()
     for _ in range(steps):
         per_pass += sv.apply_circuit_timed(fc)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    region_marker()
     per_pass /= steps
     state_bytes = (1 << n) * amp
     alg_bytes_per_step = float(sum(i["alg_bytes"] for i in infos))
@@ -131,7 +164,7 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0):
         "dense_equivalent_gbs": dense_equiv_gbs,
         "paper_gibps_per_pass": state_bytes / (per_pass.sum() / npass * 1e-3) / 2**30,
         "event_ms_per_step": float(per_pass.sum()),
-        "kernels": kern, "dominant": dominant,
+        "kernels": kern, "dominant": dominant, "tune": tune,
     }
     out["blocked"] = run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, out["ms_per_step"])
     del sv, psi
@@ -743,15 +776,37 @@ def recorded_traffic(kernel, workload="qft30_c128"):
     return None
 
 
-def summarize_kernel_trace(stats_csv, command, name_filter=None):
-    """Top kernels of a rocprofv3 --stats CSV (with name_filter, only kernels
-    whose name contains it), headed by the command and the digests of the
-    kernel sources."""
+def timed_region_stats(trace_csv):
+    """Per-kernel statistics of the dispatches in a rocprofv3 per-dispatch
+    kernel trace that lie between the first two region markers (the first
+    timed region of the run), in the layout of the --stats CSV."""
+    import collections
     import csv
-    rows = list(csv.DictReader(open(stats_csv)))
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Dispatch_Id"]))
+    marks = [i for i, r in enumerate(rows) if "k_stream_scale" in r["Kernel_Name"] and int(r["Grid_Size_X"]) == 256]
+    if len(marks) < 2:
+        raise SystemExit(f"{trace_csv}: fewer than two region markers")
+    per = collections.defaultdict(list)
+    for r in rows[marks[0] + 1:marks[1]]:
+        per[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    total = sum(sum(v) for v in per.values())
+    out = [{"Name": k, "Calls": len(v), "AverageNs": sum(v) / len(v), "TotalDurationNs": sum(v), "MinNs": min(v),
+            "MaxNs": max(v), "Percentage": 100.0 * sum(v) / total} for k, v in per.items()]
+    return sorted(out, key=lambda r: -r["TotalDurationNs"])
+
+
+def summarize_kernel_trace(stats_csv, command, name_filter=None):
+    """Top kernels of a rocprofv3 --stats CSV, or, given the per-dispatch
+    kernel trace CSV, of the first timed region's dispatches only (with
+    name_filter, only kernels whose name contains it), headed by the command
+    and the digests of the kernel sources."""
+    import csv
+    region = "Dispatch_Id" in open(stats_csv).readline()
+    rows = timed_region_stats(stats_csv) if region else list(csv.DictReader(open(stats_csv)))
     if name_filter:
         rows = [r for r in rows if name_filter in r["Name"]]
-    out = [f"# rocprofv3 kernel-trace summary" + (f" (kernels matching {name_filter})" if name_filter else ""),
+    out = [f"# rocprofv3 kernel-trace summary" + (f" (kernels matching {name_filter})" if name_filter else "") +
+           (" of the first timed region (dispatches between its two marker dispatches)" if region else ""),
            f"# command: {command}", digest_header(),
            f"{'kernel':78s} {'calls':>6s} {'avg_ms':>9s} {'total_ms':>10s} {'min_ms':>8s} {'max_ms':>8s} {'pct':>6s}"]
     for r in rows[:16]:
@@ -830,6 +885,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--k-max", type=int, default=5)
+    ap.add_argument("--tune-reps", type=int, default=3,
+                    help="launches per candidate shape when tuning the QFT's direct passes (0: knob shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-vqa", action="store_true")
@@ -913,11 +970,11 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     progress("qft complex128")
-    main_run = run_gpu(args.n, args.k_max, "c128", args.steps, args.warmup)
+    main_run = run_gpu(args.n, args.k_max, "c128", args.steps, args.warmup, tune_reps=args.tune_reps)
     extras = {}
     if not args.no_c64:
         progress("qft complex64")
-        extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup)
+        extras["c64"] = run_gpu(args.n, args.k_max, "c64", args.steps, args.warmup, tune_reps=args.tune_reps)
     progress("qft complex64 error against complex128")
     c64_err = None if args.no_c64 else qft_c64_error(args.n, args.k_max)
     dom = main_run["kernels"][main_run["dominant"]]

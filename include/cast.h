@@ -197,6 +197,35 @@ cast_status circuit_passes(const cast_fused *f, int n, cast_dtype dt, size_t *n_
 cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
                               int *kernel, int *tables, double *alg_bytes, double *flops);
 
+/* Launch shapes of the direct passes (kernel 0).  A direct pass walks its
+ * (group, block) work items in runs of 2^chunk_log groups of one block and
+ * visits its 2^it_bits iterations in an order rotated left by rot bits
+ * (rot 0: address order; needs a power-of-two iteration count, else 0).
+ * Which rate a shape reaches depends on how the gate's planes fall onto the
+ * DRAM channels and banks, so no one knob value suits every pass (the
+ * paper's cost model is likewise measured, Sec. III-C).  The shape is kept
+ * per pass in the list's schedule for (n, dt); -1 means the knob's value
+ * (direct_rot / direct_chunk_log).  Every shape computes each amplitude with
+ * the same operations, so results are bitwise the same whatever the shape.
+ * A schedule rebuilt after a change of diag_run_tables, diag_run_qubits or
+ * use_diag starts from -1 again.
+ *
+ * circuit_pass_shape reads pass i's shape (outputs may be NULL);
+ * circuit_set_pass_shape sets it (rot -1..16, chunk_log -1 or 6..16; a
+ * chunk_log above n - k acts as n - k), CAST_EINVAL for i out of range. */
+cast_status circuit_pass_shape(const cast_fused *f, int n, cast_dtype dt, size_t i, int *rot, int *chunk_log);
+cast_status circuit_set_pass_shape(cast_fused *f, int n, cast_dtype dt, size_t i, int rot, int chunk_log);
+
+/* Chooses each direct pass's launch shape by measurement on sv's device:
+ * the knobs' shape, run lengths 2^8, 2^10 and 2^12 groups, then rotations
+ * 2, 4 and 6 at the best run length, each launched reps times (1..100; the
+ * minimum counts); a shape other than the knobs' is kept only when it is more
+ * than 1 % faster.  The passes are applied to sv in place, so its amplitudes
+ * change (they stay normalised: every pass is unitary).  *before_ms and
+ * *after_ms (may be NULL) receive the summed minimum times of the direct
+ * passes with the knobs' shapes and with the chosen ones.  Synchronous. */
+cast_status circuit_tune(cast_sv *sv, cast_fused *f, int reps, double *before_ms, double *after_ms);
+
 /* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct
  * gather), 1 (LDS tile), 2 (LDS tile, two buffers), 3 (elementwise diagonal)
  * or -1 (identity, skipped), *d the block dimension,

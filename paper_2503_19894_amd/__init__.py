@@ -74,6 +74,11 @@ SIGNATURES = {
     "circuit_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t), _c_int_p,
                                          _c_int_p, _c_double_p, _c_double_p]),
+    "circuit_pass_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _c_int_p,
+                                          _c_int_p]),
+    "circuit_set_pass_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_size_t,
+                                              ctypes.c_int, ctypes.c_int]),
+    "circuit_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _c_double_p, _c_double_p]),
     "fused_pass_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _c_int_p,
                                        _c_int_p, _c_double_p, _c_double_p]),
     "apply_circuit_blocked": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -388,6 +393,17 @@ class FusedCircuit:
                         "alg_bytes": b.value, "flops": f.value})
         return out
 
+    def pass_shape(self, dtype, i):
+        """(rot, chunk_log) launch shape of pass i (-1: the knob's value)."""
+        dt = C128 if dtype == torch.complex128 else C64
+        r, c = ctypes.c_int(), ctypes.c_int()
+        circuit_pass_shape(self.handle, self.n, dt, i, ctypes.byref(r), ctypes.byref(c))
+        return r.value, c.value
+
+    def set_pass_shape(self, dtype, i, rot=-1, chunk_log=-1):
+        dt = C128 if dtype == torch.complex128 else C64
+        circuit_set_pass_shape(self.handle, self.n, dt, i, int(rot), int(chunk_log))
+
     def blocked_passes(self, dtype):
         """The cache-blocked grouping on this circuit's n qubits in `dtype`:
         one dict per HBM pass with the fused gates it covers and, for a
@@ -457,6 +473,14 @@ class StateVector:
         out = (ctypes.c_float * max(1, nf))()
         apply_circuit_timed(self.handle, fused.handle, out)
         return np.array(out[:nf], dtype=np.float64)
+
+    def tune_circuit(self, fused: FusedCircuit, reps=3):
+        """Measures and keeps each direct pass's launch shape (circuit_tune);
+        changes this state's amplitudes.  Returns (ms before, ms after) of
+        the direct passes."""
+        b, a = ctypes.c_double(), ctypes.c_double()
+        circuit_tune(self.handle, fused.handle, int(reps), ctypes.byref(b), ctypes.byref(a))
+        return b.value, a.value
 
     def apply_circuit_blocked(self, fused: FusedCircuit):
         """Applies the circuit with several fused gates per HBM pass."""

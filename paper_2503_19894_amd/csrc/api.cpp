@@ -695,7 +695,7 @@ static cast_status launch_sched_pass(cast_sv *sv, cast_fused *f, const Schedule 
     if (sp.kind == 6) return launch_diag_run(sv->data, sv->n, sv->dt, sp, sc.dev.ptr, sv->stream);
     const size_t rsz = sv->dt == CAST_C128 ? 8 : 4;
     const void *dm = (const char *)f->dev[sv->dt].ptr + f->dev_off[sv->dt][sp.first] * rsz;
-    return launch_pass(sv->data, sv->n, sv->dt, f->plans[sp.first], dm, sv->stream);
+    return launch_pass(sv->data, sv->n, sv->dt, f->plans[sp.first], dm, sv->stream, &sp.shape);
 }
 
 static cast_status prepare_circuit(cast_sv *sv, const cast_fused *fc, cast_fused **f, Schedule **sc) {
@@ -742,6 +742,103 @@ cast_status apply_circuit_timed(cast_sv *sv, const cast_fused *fc, float *pass_m
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return rc;
+}
+
+cast_status circuit_pass_shape(const cast_fused *fc, int n, cast_dtype dt, size_t i, int *rot, int *chunk_log) {
+    if (!fc) return fail(CAST_EINVAL, "fused list is NULL");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n != fc->n) return fail(CAST_EINVAL, "n differs from the fused list's");
+    Schedule *sc;
+    if (cast_status rc = get_schedule(const_cast<cast_fused *>(fc), n, dt, false, &sc)) return rc;
+    if (i >= sc->passes.size()) return fail(CAST_EINVAL, "pass index out of range");
+    if (rot) *rot = sc->passes[i].shape.rot;
+    if (chunk_log) *chunk_log = sc->passes[i].shape.chunk_log;
+    return CAST_OK;
+}
+
+cast_status circuit_set_pass_shape(cast_fused *fc, int n, cast_dtype dt, size_t i, int rot, int chunk_log) {
+    if (!fc) return fail(CAST_EINVAL, "fused list is NULL");
+    if (dt != CAST_C64 && dt != CAST_C128) return fail(CAST_EINVAL, "bad dtype");
+    if (n != fc->n) return fail(CAST_EINVAL, "n differs from the fused list's");
+    if (rot < -1 || rot > 16) return fail(CAST_EINVAL, "rot must be -1..16");
+    if (chunk_log != -1 && (chunk_log < 6 || chunk_log > 16)) return fail(CAST_EINVAL, "chunk_log must be -1 or 6..16");
+    Schedule *sc;
+    if (cast_status rc = get_schedule(fc, n, dt, false, &sc)) return rc;
+    if (i >= sc->passes.size()) return fail(CAST_EINVAL, "pass index out of range");
+    sc->passes[i].shape.rot = rot;
+    sc->passes[i].shape.chunk_log = chunk_log;
+    return CAST_OK;
+}
+
+cast_status circuit_tune(cast_sv *sv, cast_fused *fc, int reps, double *before_ms, double *after_ms) {
+    if (reps < 1 || reps > 100) return fail(CAST_EINVAL, "reps must be 1..100");
+    cast_fused *f;
+    Schedule *sc;
+    if (cast_status rc = prepare_circuit(sv, fc, &f, &sc)) return rc;
+    const int n = sv->n;
+    const cast_dtype dt = sv->dt;
+    const Tuning &tu = tuning();
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto &e : ev) CAST_HIP_TRY(hipEventCreate(&e));
+    cast_status rc = CAST_OK;
+    // minimum over reps of one launch of pass sp with shape sh (ms)
+    auto time_shape = [&](SchedPass &sp, const PassShape &sh, double *ms) -> cast_status {
+        const PassShape keep = sp.shape;
+        sp.shape = sh;
+        cast_status r = CAST_OK;
+        for (int j = 0; j < reps && !r; ++j) {
+            if (hipEventRecord(ev[2 * j], sv->stream) != hipSuccess) r = fail(CAST_EHIP, "hipEventRecord");
+            if (!r) r = launch_sched_pass(sv, f, *sc, sp);
+            if (!r && hipEventRecord(ev[2 * j + 1], sv->stream) != hipSuccess) r = fail(CAST_EHIP, "hipEventRecord");
+        }
+        sp.shape = keep;
+        if (r) return r;
+        if (hipEventSynchronize(ev[2 * reps - 1]) != hipSuccess) return fail(CAST_EHIP, "hipEventSynchronize");
+        double best = 1e30;
+        for (int j = 0; j < reps; ++j) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[2 * j], ev[2 * j + 1]) != hipSuccess) return fail(CAST_EHIP, "hipEventElapsedTime");
+            best = std::min(best, (double)t);
+        }
+        *ms = best;
+        return CAST_OK;
+    };
+    double before = 0, after = 0;
+    for (size_t i = 0; i < sc->passes.size() && !rc; ++i) {
+        SchedPass &sp = sc->passes[i];
+        if (sp.kind != 0 || pass_kernel_kind(n, dt, f->plans[sp.first]) != 0) continue;
+        const int k = f->plans[sp.first].k;
+        // the knobs' shape first, then run lengths, then rotations at the best run length
+        const PassShape knob{-1, -1};
+        double t_knob = 0;
+        if ((rc = time_shape(sp, knob, &t_knob))) break;
+        PassShape best = knob;
+        double t_best = t_knob;
+        int best_cl = std::min(std::max(tu.direct_chunk_log[dt], 6), n - k);
+        for (int cl : {8, 10, 12}) {
+            if (cl > n - k || cl == best_cl) continue;
+            double t = 0;
+            if ((rc = time_shape(sp, PassShape{0, cl}, &t))) break;
+            if (t < t_best) t_best = t, best = PassShape{0, cl}, best_cl = cl;
+        }
+        for (int rot : {2, 4, 6}) {
+            if (rc) break;
+            double t = 0;
+            if ((rc = time_shape(sp, PassShape{rot, best_cl}, &t))) break;
+            if (t < t_best) t_best = t, best = PassShape{rot, best_cl};
+        }
+        if (rc) break;
+        // a shape other than the knobs' must win by more than timing noise
+        if (t_best > 0.99 * t_knob) best = knob, t_best = t_knob;
+        sp.shape = best;
+        before += t_knob;
+        after += t_best;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    if (before_ms) *before_ms = before;
+    if (after_ms) *after_ms = after;
+    return CAST_OK;
 }
 
 cast_status circuit_passes(const cast_fused *fc, int n, cast_dtype dt, size_t *n_passes) {

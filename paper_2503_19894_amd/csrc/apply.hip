@@ -699,7 +699,8 @@ static int direct_ipt(int D, cast_dtype dt) {
 }
 
 template <typename R>
-static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const PassArgs &a, hipStream_t s) {
+static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const PassArgs &a, hipStream_t s,
+                                int rot_override) {
     const int ipt = direct_ipt(D, dt);
     const bool nt = tuning().direct_nt[dt] != 0;
     const uint64_t items = a.ngroups * a.nblk;
@@ -712,13 +713,16 @@ static hipError_t launch_direct(int D, cast_dtype dt, R *psi, const R *m, const 
     {
         // rotated iteration order for passes whose lowest target lies in
         // [direct_rot_lo, direct_rot_hi] (needs a power-of-two iteration count)
+        // (a pass's own shape overrides the knobs)
         const Tuning &tu = tuning();
         const uint64_t nfull = items / (256ull * ipt);
         const int q0 = __builtin_ctzll(a.lowmask[0] + 1);   // lowest target
-        if (tu.direct_rot[dt] > 0 && nfull > 1 && !(nfull & (nfull - 1)) && q0 >= tu.direct_rot_lo[dt] &&
-            q0 <= tu.direct_rot_hi[dt]) {
+        const int rot = rot_override >= 0 ? rot_override
+                        : (q0 >= tu.direct_rot_lo[dt] && q0 <= tu.direct_rot_hi[dt]) ? tu.direct_rot[dt]
+                                                                                      : 0;
+        if (rot > 0 && nfull > 1 && !(nfull & (nfull - 1))) {
             b.it_bits = __builtin_ctzll(nfull);
-            b.rot = tu.direct_rot[dt] < b.it_bits ? tu.direct_rot[dt] : 0;
+            b.rot = rot < b.it_bits ? rot : 0;
         }
     }
     switch (ipt * 2 + (nt ? 1 : 0)) {
@@ -878,7 +882,7 @@ static hipError_t launch_mfma(int D, bool tile, bool m3, bool pre, R *psi, const
 }
 
 cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
-                        hipStream_t stream) {
+                        hipStream_t stream, const PassShape *shape) {
     if (p.identity()) return CAST_OK;
     const Tuning &tu = tuning();
     const int k = p.k, D = p.d;
@@ -993,12 +997,14 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
         for (int i = 0; i < k; ++i) a.lowmask[i] = (1ull << p.q[i]) - 1;
         a.ngroups = 1ull << (n - k);
         // ngroups >= 64 (n - k >= 6), so a run of 2^chunk_log items is one block's groups
-        a.chunk_log = tu.direct_chunk_log[dt] < 6 ? 6 : tu.direct_chunk_log[dt];
+        const int cl = shape && shape->chunk_log >= 0 ? shape->chunk_log : tu.direct_chunk_log[dt];
+        a.chunk_log = cl < 6 ? 6 : cl;
         if (a.chunk_log > n - k) a.chunk_log = n - k;
+        const int rot = shape ? shape->rot : -1;
         if (dt == CAST_C128)
-            e = launch_direct<double>(D, dt, (double *)psi, (const double *)dmat, a, stream);
+            e = launch_direct<double>(D, dt, (double *)psi, (const double *)dmat, a, stream, rot);
         else
-            e = launch_direct<float>(D, dt, (float *)psi, (const float *)dmat, a, stream);
+            e = launch_direct<float>(D, dt, (float *)psi, (const float *)dmat, a, stream, rot);
     } else {
         int tb = tu.tile_bits[dt];
         if (twobuf) tb = 12;

@@ -134,9 +134,16 @@ void pack_plan(const PassPlan &p, std::vector<R> &dst) {
 }
 int pass_kernel_kind(int n, cast_dtype dt, const PassPlan &p);
 
+// Launch shape of one direct pass, overriding the knobs (-1: the knob's
+// value): rotation of the iteration order and log2 of the block run length.
+struct PassShape {
+    int rot = -1;
+    int chunk_log = -1;
+};
+
 // Queues one pass on `stream`.  `dmat` holds the plan's blocks in dtype `dt`.
 cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, const void *dmat,
-                        hipStream_t stream);
+                        hipStream_t stream, const PassShape *shape = nullptr);
 
 // Uploads a plan's matrices (cast to dt) into a new device buffer; the host
 // staging is synchronous (the buffer is ready when this returns).
@@ -164,6 +171,7 @@ struct SchedPass {
     std::vector<PhaseTable> tabs;    // kind 6
     size_t tab_off = 0;              // kind 6: entry offset of its tables in the device buffer
     double active_amps = 0;          // kind 6: amplitudes at which some table differs from 1
+    PassShape shape;                 // kind 0: launch shape (circuit_tune)
 };
 struct Schedule {
     int n = 0;

@@ -178,3 +178,22 @@ def test_device_byte_cap_gives_enomem():
     assert r.returncode == 0, r.stderr
     out = r.stdout.strip().splitlines()[-1]
     assert out.startswith("-2 ") and "CAST_MAX_DEVICE_BYTES" in out, out
+
+
+def test_pass_shape_host_side():
+    """Per-pass launch shapes live in the list's schedule per dtype; bad
+    values and indices are rejected without device work."""
+    import torch
+    from circuits import qft
+    fc = cast.FusedCircuit(20, qft(20), k_max=5)
+    sched = fc.schedule(torch.complex128)
+    i = next(j for j, p in enumerate(sched) if p["kernel"] == 0)
+    assert fc.pass_shape(torch.complex128, i) == (-1, -1)
+    fc.set_pass_shape(torch.complex128, i, 2, 10)
+    assert fc.pass_shape(torch.complex128, i) == (2, 10)
+    assert fc.pass_shape(torch.complex64, i) == (-1, -1)
+    assert _code(fc.set_pass_shape, torch.complex128, i, 17, 10) == EINVAL
+    assert _code(fc.set_pass_shape, torch.complex128, i, 0, 5) == EINVAL
+    assert _code(fc.set_pass_shape, torch.complex128, len(sched), 0, 8) == EINVAL
+    assert _code(cast.circuit_tune, None, fc.handle, 3, None, None) == EINVAL
+    assert fc.pass_shape(torch.complex128, i) == (2, 10)

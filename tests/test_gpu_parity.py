@@ -202,6 +202,52 @@ def test_direct_rotated_order(dtype, rot):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
+def test_pass_shapes_and_tuner(dtype):
+    """Per-pass launch shapes (rotation, block-run length) set by hand on
+    every direct pass, and the shapes the tuner picks: the same circuit
+    gives bitwise the same state as with the knobs' shapes, and matches the
+    oracle."""
+    n = 17
+    rng = np.random.default_rng(29)
+    gates = qft(n)
+    for qs, d in (((4, 6, 9, 12, 16), 1), ((5, 7, 8, 15), 2), ((10, 11, 13), 3)):
+        k = len(qs)
+        u = haar_unitary(1 << d, rng)
+        ph = np.exp(1j * rng.uniform(0.1, 6.0, 1 << (k - d)))
+        gates.append(Gate("unitary", qs, matrix=np.kron(np.diag(ph), u)))
+    psi0 = random_state(n, seed=8, workload=3)
+    want = oracle.run_circuit(n, gates, psi0)
+    fc = cast.FusedCircuit(n, gates, k_max=4)
+    sched = fc.schedule(dtype)
+    direct = [i for i, p in enumerate(sched) if p["kernel"] == 0]
+    assert direct
+    sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+    sv.apply_circuit(fc)
+    ref = sv.tensor.clone()
+    shapes = [(1, 6), (2, 9), (5, 12), (3, 16), (0, 7)]
+    for j, i in enumerate(direct):
+        fc.set_pass_shape(dtype, i, *shapes[j % len(shapes)])
+    assert fc.pass_shape(dtype, direct[0]) == shapes[0]
+    sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
+    sv.apply_circuit(fc)
+    torch.cuda.synchronize()
+    assert torch.equal(sv.tensor, ref)
+    # the tuner applies passes to the state it is given; then start again
+    for i in direct:
+        fc.set_pass_shape(dtype, i, -1, -1)
+    before, after = sv.tune_circuit(fc, reps=2)
+    chosen = [fc.pass_shape(dtype, i) for i in direct]
+    sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
+    sv.apply_circuit(fc)
+    torch.cuda.synchronize()
+    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, ms {before:.4f} -> {after:.4f}")
+    assert after <= before
+    assert torch.equal(sv.tensor, ref)
+    err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
 def test_tile_idle_runs_skipped(dtype):
     """LDS-tile passes whose identity blocks are selected by high targets
     (controlled gates with a low target and high controls, a low-target
