@@ -6,7 +6,7 @@ fusion check uses (one pass of a k-qubit gate whose nonzero pattern spans a
 d-dimensional XOR subspace), then writes both to tuning_gfx950.json next to
 the library, which the binding applies at import.
 
-    python paper_2503_19894_amd/autotune.py [--n 28] [--out PATH]
+    python paper_2503_19894_amd/autotune.py [--n 30] [--out PATH]
 
 The cost table follows the paper's CostModel idea (Sec. III-C): time gates of
 varied size and sparsity on the target and let fusion consult the table.
@@ -233,7 +233,7 @@ def path_costs(n, dtype, log):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--out", default=os.path.join(HERE, "tuning_gfx950.json"))
     ap.add_argument("--path-costs-only", action="store_true",
                     help="keep the knobs and cost table of the existing file; measure only the path costs")
@@ -261,6 +261,9 @@ def main():
     for dname, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
         log(f"{dname}: knobs")
         result["knobs"][dname] = tune_knobs(args.n, dtype, log)
+        # the batched programs' tile size is measured on the batch workloads
+        # (bench.py --vqa-only / --tfim-only), not on this suite: carried over
+        result["knobs"][dname]["batch_tile_bits"] = cast.get_tuning("batch_tile_bits", dtype)
         log(f"{dname}: cost table (ms per 2^30 amplitudes)")
         result["cost"][dname] = cost_table(args.n, dtype, log)
         log(f"{dname}: path costs")
