@@ -22,6 +22,10 @@ __device__ __forceinline__ uint64_t ins0(uint64_t g, int q) {
     const uint64_t lm = (1ull << q) - 1;
     return ((g & ~lm) << 1) | (g & lm);
 }
+__device__ __forceinline__ uint32_t ins0_32(uint32_t g, int q) {
+    const uint32_t lm = (1u << q) - 1;
+    return ((g & ~lm) << 1) | (g & lm);
+}
 
 // The read-only tables (gate matrices, gate and sweep records) are read
 // through the constant address space.  Nothing in a kernel writes them, so
@@ -231,8 +235,24 @@ __device__ __forceinline__ void reg_inner(const V *l, const V *x, uint32_t xl, u
     }
 }
 
-__device__ __forceinline__ double wave_sum64(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum over a wave's 64 lanes with DPP moves, which stay in the vector unit
+// (cross-lane shuffles go through the LDS crossbar and wait on it): pairs and
+// quads by quad permutations, rows of 16 by shifts right by 4 and 8 (lanes
+// with no source add 0), then lane 15 of each row into the next row and
+// lane 31 into the upper half.  Lane 63 ends with the total.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_total63(double v) {
+    v += dpp_move<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -368,38 +388,49 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
     // tile bits once, applies the sweep's gates in registers in order (taking
     // each inner product right before its gate), and writes the group back
     const uint32_t groups = 1u << (rec->tb - 3);
+    char *tpb = reinterpret_cast<char *>(tp), *tlb = reinterpret_cast<char *>(tl);
     for (uint32_t sw = rec->sw0; sw < rec->sw1; ++sw) {
         const SegSweep SW = load_sweep(cptr(d.sweeps) + sw);
-        uint32_t off[8];
+        // bat<S> is linear over GF(2) (shifts, masks and XORs) and a group's
+        // base and the sweep offsets have disjoint bits, so the LDS slot of
+        // base | off[j] is bat(base) ^ bat(off[j]): the eight swizzled
+        // offsets are wave-uniform and each access costs one XOR
+        // (byte offsets: the XOR of two multiples of sizeof(V) is one)
+        uint32_t so[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            off[j] = ((j & 1) ? (1u << SW.b[0]) : 0u) | ((j & 2) ? (1u << SW.b[1]) : 0u) |
-                     ((j & 4) ? (1u << SW.b[2]) : 0u);
+            so[j] = bat<S>(((j & 1) ? (1u << SW.b[0]) : 0u) | ((j & 2) ? (1u << SW.b[1]) : 0u) |
+                           ((j & 4) ? (1u << SW.b[2]) : 0u)) * (uint32_t)sizeof(V);
         for (uint32_t g0 = 0; g0 < groups; g0 += blockDim.x) {
             const uint32_t g = g0 + threadIdx.x;
             const bool act = g < groups;
-            uint32_t base = 0;
+            uint32_t bb = 0;
             V x[8], l[8];
             if (act) {
-                base = (uint32_t)ins0(ins0(ins0(g, SW.b[0]), SW.b[1]), SW.b[2]);
+                bb = bat<S>(ins0_32(ins0_32(ins0_32(g, SW.b[0]), SW.b[1]), SW.b[2])) * (uint32_t)sizeof(V);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) x[j] = tp[bat<S>(base | off[j])];
+                for (int j = 0; j < 8; ++j) x[j] = *reinterpret_cast<const V *>(tpb + (bb ^ so[j]));
                 if (adj) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) l[j] = tl[bat<S>(base | off[j])];
+                    for (int j = 0; j < 8; ++j) l[j] = *reinterpret_cast<const V *>(tlb + (bb ^ so[j]));
                 }
             }
             int p = SW.p0;
+            // the next gate's record is requested while this one is applied,
+            // so its latency overlaps the matrix reads of this gate
+            SegGate Gn = load_gate(cptr(d.segs) + SW.g0);
             for (uint32_t gi = SW.g0; gi < SW.g1; ++gi) {
-                const SegGate G = load_gate(cptr(d.segs) + gi);
+                const SegGate G = Gn;
+                if (gi + 1 < SW.g1) Gn = load_gate(cptr(d.segs) + gi + 1);
                 if (adj && G.slot >= 0) {
                     double re = 0.0, im = 0.0;
                     if (act) reg_inner(l, x, G.xl, G.zl, &re, &im);
-                    re = wave_sum64(re);
-                    im = wave_sum64(im);
-                    if (lane == 0) {
-                        gsum[(p * 4 + wave) * 2] += re;
-                        gsum[(p * 4 + wave) * 2 + 1] += im;
+                    re = wave_total63(re);
+                    im = wave_total63(im);
+                    // one wave adds into its own slot, in program order
+                    if (lane == 63) {
+                        atomicAdd(&gsum[(p * 4 + wave) * 2], re);
+                        atomicAdd(&gsum[(p * 4 + wave) * 2 + 1], im);
                     }
                     ++p;
                 }
@@ -411,10 +442,10 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
             }
             if (act) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) tp[bat<S>(base | off[j])] = x[j];
+                for (int j = 0; j < 8; ++j) *reinterpret_cast<V *>(tpb + (bb ^ so[j])) = x[j];
                 if (adj) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) tl[bat<S>(base | off[j])] = l[j];
+                    for (int j = 0; j < 8; ++j) *reinterpret_cast<V *>(tlb + (bb ^ so[j])) = l[j];
                 }
             }
         }
