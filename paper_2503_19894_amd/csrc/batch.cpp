@@ -223,6 +223,53 @@ static bool batch_reorder() {
 // roughly halves the segments of the circuit-order cut, since a layer's
 // rotations on the qubits of one tile need not wait for the rest of the
 // layer.
+// Orders the gates of one segment (given in a valid application order) so
+// that consecutive gates share few qubits: the kernel applies each run of
+// gates on at most three qubits (a register sweep) with one LDS round trip
+// and one barrier, so fewer, longer runs cost less.  List scheduling under
+// the same dependence rule as the segments: a run is grown from ready gates,
+// first those whose qubits it already holds, then the one adding the fewest
+// new qubits (earliest on ties), until no ready gate fits three qubits.  On
+// a layered ansatz this interleaves the rotations of neighbouring qubits
+// with the entangling gates between them (RY, RZ on q and q + 1, then their
+// CZ) instead of running each rotation layer across the whole tile.
+static std::vector<int> cluster_sweeps(const std::vector<int> &seg, const std::vector<uint64_t> &gmask,
+                                       const std::vector<char> &gdiag) {
+    const int n = (int)seg.size();
+    std::vector<std::vector<int>> succ(n);
+    std::vector<int> indeg(n, 0);
+    for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b)
+            if ((gmask[seg[a]] & gmask[seg[b]]) && !(gdiag[seg[a]] && gdiag[seg[b]])) {
+                succ[a].push_back(b);
+                ++indeg[b];
+            }
+    std::vector<int> ready, out;
+    for (int a = 0; a < n; ++a)
+        if (!indeg[a]) ready.push_back(a);
+    while ((int)out.size() < n) {
+        uint64_t bits = 0;
+        for (;;) {
+            int pick = -1, best_new = 4;
+            for (size_t r = 0; r < ready.size(); ++r) {
+                const uint64_t m = gmask[seg[ready[r]]];
+                const int nw = __builtin_popcountll(m & ~bits);
+                if (__builtin_popcountll(bits | m) > 3) continue;
+                if (nw < best_new) pick = (int)r, best_new = nw;   // ready is ascending: earliest on ties
+            }
+            if (pick < 0 && bits == 0) pick = 0;   // (a gate on more than three qubits runs alone)
+            if (pick < 0) break;
+            const int a = ready[pick];
+            ready.erase(ready.begin() + pick);
+            out.push_back(seg[a]);
+            bits |= gmask[seg[a]];
+            for (int b : succ[a])
+                if (--indeg[b] == 0) ready.insert(std::lower_bound(ready.begin(), ready.end(), b), b);
+        }
+    }
+    return out;
+}
+
 static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &gmask, const std::vector<char> &gdiag,
                                                    int tb, bool reverse, bool reorder) {
     const int L = (int)gmask.size();
@@ -296,7 +343,7 @@ static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &
             for (int b : succ[p])
                 if (--indeg[b] == 0) ready.insert(std::lower_bound(ready.begin(), ready.end(), b), b);
         }
-        segs.push_back(cur);
+        segs.push_back(cluster_sweeps(cur, gmask, gdiag));
     }
     return segs;
 }
