@@ -91,25 +91,33 @@ static void sorted_matrix(int k, const int *qubits, const std::vector<cplx> &m, 
     *out = p.full;
 }
 
-static void put_matrix(cast_batch *b, uint64_t off, const std::vector<cplx> &m, bool dagger, int k) {
+// Writes a gate's matrix entry into the pinned table in the state dtype: its
+// 2^k x 2^k entries row-major (dagger: those of the adjoint), or for a
+// two-qubit diagonal form its four diagonal entries first, the layout the
+// batched kernels read.
+static void put_matrix(cast_batch *b, uint64_t off, const cplx *m, bool dagger, int k, bool diag_form) {
     const int D = 1 << k;
-    for (int r = 0; r < D; ++r)
-        for (int c = 0; c < D; ++c) {
-            const cplx z = dagger ? std::conj(m[(size_t)c * D + r]) : m[(size_t)r * D + c];
-            const size_t e = (size_t)(off + (uint64_t)r * D + c);
-            if (b->dt == CAST_C128) {
-                ((double *)b->h_mats)[2 * e] = z.real();
-                ((double *)b->h_mats)[2 * e + 1] = z.imag();
-            } else {
-                ((float *)b->h_mats)[2 * e] = (float)z.real();
-                ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
-            }
+    auto put = [&](uint64_t e, cplx z) {
+        if (b->dt == CAST_C128) {
+            ((double *)b->h_mats)[2 * e] = z.real();
+            ((double *)b->h_mats)[2 * e + 1] = z.imag();
+        } else {
+            ((float *)b->h_mats)[2 * e] = (float)z.real();
+            ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
         }
+    };
+    if (diag_form && k == 2) {
+        for (int r = 0; r < D; ++r) put(off + r, dagger ? std::conj(m[r * D + r]) : m[r * D + r]);
+        for (int e = D; e < D * D; ++e) put(off + e, 0.0);
+        return;
+    }
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) put(off + (uint64_t)r * D + c, dagger ? std::conj(m[(size_t)c * D + r]) : m[(size_t)r * D + c]);
 }
 
 // exp(-i a P / 2) = cos(a/2) I - i sin(a/2) P with P a Pauli string (2-bit
 // letters in local bit order): P has one nonzero per row, at column r ^ x.
-static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double angle, bool dagger) {
+static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double angle, bool dagger, bool diag_form) {
     const int D = 1 << k;
     const double c = std::cos(angle / 2), s = std::sin(angle / 2) * (dagger ? -1.0 : 1.0);
     uint32_t x = 0;
@@ -131,18 +139,7 @@ static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double an
         m[r * D + (r ^ (int)x)] += cplx(0, -1) * s * p;  // dagger: conj of a Hermitian P's coefficient
     }
     // U^dag = cos I + i sin P; the loop above used -s for it, and P is Hermitian
-    for (int r = 0; r < D; ++r)
-        for (int cc = 0; cc < D; ++cc) {
-            const cplx z = m[r * D + cc];
-            const size_t e = (size_t)(off + (uint64_t)r * D + cc);
-            if (b->dt == CAST_C128) {
-                ((double *)b->h_mats)[2 * e] = z.real();
-                ((double *)b->h_mats)[2 * e + 1] = z.imag();
-            } else {
-                ((float *)b->h_mats)[2 * e] = (float)z.real();
-                ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
-            }
-        }
+    put_matrix(b, off, m, false, k, diag_form);
 }
 
 static cast_status queue_program(cast_batch *b) {
@@ -539,6 +536,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         }
         state_elems += 2ull << n;  // psi and lambda
     }
+    if (mat_entries > 0xffffffffull) return bail(fail(CAST_EUNSUPPORTED, "batch matrix table exceeds 2^32 entries"));
     b->mat_entries = mat_entries;
     b->result_doubles = res;
     // ---- instance groups (consecutive instances whose psi and lambda fit the
@@ -644,18 +642,19 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                         const int l = gl[q];
                         SegGate sgt;
                         memset(&sgt, 0, sizeof sgt);
-                        sgt.k = ip.gates[l].k;
-                        sgt.t0 = loc[pos[ip.sq0[l]]];
-                        sgt.t1 = sgt.k == 2 ? loc[pos[ip.sq1[l]]] : -1;
+                        const int k = ip.gates[l].k;
+                        const int t0 = loc[pos[ip.sq0[l]]];
+                        const int t1 = k == 2 ? loc[pos[ip.sq1[l]]] : -1;
                         sgt.slot = op.kind == BK_ADJ ? ip.gslot[l] : -1;
                         // generator masks: gate-local bit 0 / 1 -> sweep bits t0 / t1
-                        for (int bb = 0; bb < sgt.k; ++bb) {
-                            const int sb = bb == 0 ? sgt.t0 : sgt.t1;
-                            if ((ip.xl[l] >> bb) & 1u) sgt.xl |= 1u << sb;
-                            if ((ip.zl[l] >> bb) & 1u) sgt.zl |= 1u << sb;
+                        uint32_t xl = 0, zl = 0;
+                        for (int bb = 0; bb < k; ++bb) {
+                            const int sb = bb == 0 ? t0 : t1;
+                            if ((ip.xl[l] >> bb) & 1u) xl |= 1u << sb;
+                            if ((ip.zl[l] >> bb) & 1u) zl |= 1u << sb;
                         }
-                        sgt.mat = op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l];
-                        sgt.form = ip.form[l];
+                        sgt.info = seg_info(k, t0, t1, ip.form[l], xl, zl, sgt.slot >= 0);
+                        sgt.mat = (uint32_t)(op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l]);
                         if (sgt.slot >= 0) ++nparam;
                         segs.push_back(sgt);
                     }
@@ -727,8 +726,8 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         return bail(fail(CAST_ENOMEM, "pinned result buffer"));
     for (auto &ip : b->inst)
         for (size_t l = 0; l < ip.gates.size(); ++l) {
-            put_matrix(b, ip.mat_fwd[l], ip.fixed[l], false, ip.gates[l].k);
-            put_matrix(b, ip.mat_adj[l], ip.fixed[l], true, ip.gates[l].k);
+            put_matrix(b, ip.mat_fwd[l], ip.fixed[l].data(), false, ip.gates[l].k, ip.form[l] == BF_DIAG);
+            put_matrix(b, ip.mat_adj[l], ip.fixed[l].data(), true, ip.gates[l].k, ip.form[l] == BF_DIAG);
         }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(CAST_EHIP, "hipStreamCreate failed"));
@@ -789,8 +788,8 @@ cast_status batch_run(cast_batch *b, const double *const *theta, double *energie
             const cast_gate &g = ip.gates[l];
             if (g.param_id < 0) continue;
             const double a = g.param_coeff * theta[i][g.param_id];
-            bind_rotation(b, ip.mat_fwd[l], g.k, ip.gen_sorted[l], a, false);
-            bind_rotation(b, ip.mat_adj[l], g.k, ip.gen_sorted[l], a, true);
+            bind_rotation(b, ip.mat_fwd[l], g.k, ip.gen_sorted[l], a, false, ip.form[l] == BF_DIAG);
+            bind_rotation(b, ip.mat_adj[l], g.k, ip.gen_sorted[l], a, true, ip.form[l] == BF_DIAG);
         }
     }
     if (b->mode >= 1) {

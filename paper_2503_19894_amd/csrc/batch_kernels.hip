@@ -75,8 +75,22 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // Gates on a thread's 8 register amplitudes x[j], j over the sweep's three
 // tile bits.  Bit positions are template parameters so every register index
 // is a compile-time constant.
-template <int B, typename V, typename R>
-__device__ __forceinline__ void reg_apply1(V *x, CPtr<R> m) {
+// The first eight reals of a gate's matrix entry, read ahead of the gate
+// (every one-qubit form and the two-qubit diagonal need no more).
+template <typename R> struct Coef8 {
+    R c[8];
+    __device__ __forceinline__ R operator[](int i) const { return c[i]; }
+};
+template <typename R>
+__device__ __forceinline__ Coef8<R> load_coef(CPtr<R> m) {
+    Coef8<R> k;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) k.c[i] = m[i];
+    return k;
+}
+
+template <int B, typename V, typename M>
+__device__ __forceinline__ void reg_apply1(V *x, const M &m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j & (1 << B)) continue;
@@ -109,13 +123,17 @@ __device__ __forceinline__ void reg_apply2(V *x, CPtr<R> m) {
 }
 
 // Diagonal gate on sweep bits (B0, B1; B1 < 0 for one qubit): x[j] *= D[j's bits].
-template <int B0, int B1, typename V, typename R>
-__device__ __forceinline__ void reg_diag(V *x, CPtr<R> m) {
-    constexpr int K = B1 < 0 ? 1 : 2, DIM = 1 << K;
+// A one-qubit diagonal is read from its 2 x 2 matrix (entries 0 and 3), a
+// two-qubit one from its compact diagonal (the host stores its four entries
+// first).
+template <int B0, int B1, typename V, typename M>
+__device__ __forceinline__ void reg_diag(V *x, const M &m) {
+    constexpr int K = B1 < 0 ? 1 : 2;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int loc = ((j >> B0) & 1) | (B1 < 0 ? 0 : ((j >> (B1 < 0 ? 0 : B1)) & 1) << 1);
-        const R dr = m[2 * (loc * DIM + loc)], di = m[2 * (loc * DIM + loc) + 1];
+        const int e = K == 1 ? 3 * loc : loc;
+        const auto dr = m[2 * e], di = m[2 * e + 1];
         const V a = x[j];
         x[j].x = dr * a.x - di * a.y;
         x[j].y = dr * a.y + di * a.x;
@@ -123,9 +141,9 @@ __device__ __forceinline__ void reg_diag(V *x, CPtr<R> m) {
 }
 
 // Real matrix: only the real parts of the entries are read (two multiplies per entry).
-template <int B, typename V, typename R>
-__device__ __forceinline__ void reg_real1(V *x, CPtr<R> m) {
-    const R m00 = m[0], m01 = m[2], m10 = m[4], m11 = m[6];
+template <int B, typename V, typename M>
+__device__ __forceinline__ void reg_real1(V *x, const M &m) {
+    const auto m00 = m[0], m01 = m[2], m10 = m[4], m11 = m[6];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (j & (1 << B)) continue;
@@ -161,46 +179,58 @@ __device__ __forceinline__ void reg_real2(V *x, CPtr<R> m) {
     }
 }
 
+// Fields of a packed gate record (SegGate::info).
+__device__ __forceinline__ int gi_k(uint32_t i) { return 1 + (int)(i & 1u); }
+__device__ __forceinline__ int gi_t0(uint32_t i) { return (int)((i >> 1) & 3u); }
+__device__ __forceinline__ int gi_t1(uint32_t i) { return (int)((i >> 3) & 3u); }
+__device__ __forceinline__ int gi_form(uint32_t i) { return (int)((i >> 5) & 3u); }
+__device__ __forceinline__ uint32_t gi_xl(uint32_t i) { return (i >> 7) & 7u; }
+__device__ __forceinline__ uint32_t gi_zl(uint32_t i) { return (i >> 10) & 7u; }
+__device__ __forceinline__ bool gi_param(uint32_t i) { return (i >> 13) & 1u; }
+
+// One gate of a sweep: `c` holds the first eight reals of its matrix entry
+// (read ahead), `m` points at the whole entry (two-qubit dense forms).
 template <typename V, typename R>
-__device__ __forceinline__ void reg_apply(const SegGate &G, V *x, CPtr<R> m) {
-    if (G.form == BF_DIAG) {
-        if (G.k == 1) {
-            switch (G.t0) {
-                case 0: reg_diag<0, -1>(x, m); break;
-                case 1: reg_diag<1, -1>(x, m); break;
-                default: reg_diag<2, -1>(x, m); break;
+__device__ __forceinline__ void reg_apply(uint32_t info, V *x, const Coef8<R> &c, CPtr<R> m) {
+    const int k = gi_k(info), t0 = gi_t0(info), t1 = gi_t1(info), form = gi_form(info);
+    if (form == BF_DIAG) {
+        if (k == 1) {
+            switch (t0) {
+                case 0: reg_diag<0, -1>(x, c); break;
+                case 1: reg_diag<1, -1>(x, c); break;
+                default: reg_diag<2, -1>(x, c); break;
             }
-        } else if (G.t0 == 0) {
-            if (G.t1 == 1) reg_diag<0, 1>(x, m);
-            else reg_diag<0, 2>(x, m);
+        } else if (t0 == 0) {
+            if (t1 == 1) reg_diag<0, 1>(x, c);
+            else reg_diag<0, 2>(x, c);
         } else {
-            reg_diag<1, 2>(x, m);
+            reg_diag<1, 2>(x, c);
         }
         return;
     }
-    if (G.form == BF_REAL) {
-        if (G.k == 1) {
-            switch (G.t0) {
-                case 0: reg_real1<0>(x, m); break;
-                case 1: reg_real1<1>(x, m); break;
-                default: reg_real1<2>(x, m); break;
+    if (form == BF_REAL) {
+        if (k == 1) {
+            switch (t0) {
+                case 0: reg_real1<0>(x, c); break;
+                case 1: reg_real1<1>(x, c); break;
+                default: reg_real1<2>(x, c); break;
             }
-        } else if (G.t0 == 0) {
-            if (G.t1 == 1) reg_real2<0, 1>(x, m);
+        } else if (t0 == 0) {
+            if (t1 == 1) reg_real2<0, 1>(x, m);
             else reg_real2<0, 2>(x, m);
         } else {
             reg_real2<1, 2>(x, m);
         }
         return;
     }
-    if (G.k == 1) {
-        switch (G.t0) {
-            case 0: reg_apply1<0>(x, m); break;
-            case 1: reg_apply1<1>(x, m); break;
-            default: reg_apply1<2>(x, m); break;
+    if (k == 1) {
+        switch (t0) {
+            case 0: reg_apply1<0>(x, c); break;
+            case 1: reg_apply1<1>(x, c); break;
+            default: reg_apply1<2>(x, c); break;
         }
-    } else if (G.t0 == 0) {
-        if (G.t1 == 1) reg_apply2<0, 1>(x, m);
+    } else if (t0 == 0) {
+        if (t1 == 1) reg_apply2<0, 1>(x, m);
         else reg_apply2<0, 2>(x, m);
     } else {
         reg_apply2<1, 2>(x, m);
@@ -267,18 +297,14 @@ __device__ __forceinline__ SegSweep load_sweep(CPtr<SegSweep> p) {
     return w;
 }
 
-__device__ __forceinline__ SegGate load_gate(CPtr<SegGate> p) {
-    SegGate g;
-    g.k = p->k;
-    g.t0 = p->t0;
-    g.t1 = p->t1;
-    g.slot = p->slot;
-    g.xl = p->xl;
-    g.zl = p->zl;
-    g.mat = p->mat;
-    g.form = p->form;
-    g.pad = 0;
-    return g;
+struct GateOp {             // what the sweep loop reads of a gate record
+    uint32_t info, mat;
+};
+__device__ __forceinline__ GateOp load_op(CPtr<SegGate> p) {
+    GateOp o;
+    o.info = p->info;
+    o.mat = p->mat;
+    return o;
 }
 
 __device__ __forceinline__ BatchInst load_inst(CPtr<BatchInst> p) {
@@ -416,15 +442,22 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                 }
             }
             int p = SW.p0;
-            // the next gate's record is requested while this one is applied,
-            // so its latency overlaps the matrix reads of this gate
-            SegGate Gn = load_gate(cptr(d.segs) + SW.g0);
+            // read ahead: the record two gates on and the coefficients of the
+            // next gate are requested while this gate is applied, so the
+            // scalar loads of a gate never wait on each other
+            CPtr<SegGate> sg = cptr(d.segs);
+            GateOp o0 = load_op(sg + SW.g0);
+            GateOp o1 = SW.g0 + 1 < SW.g1 ? load_op(sg + SW.g0 + 1) : o0;
+            Coef8<R> cn = load_coef(mats + 2 * (uint64_t)o0.mat);
             for (uint32_t gi = SW.g0; gi < SW.g1; ++gi) {
-                const SegGate G = Gn;
-                if (gi + 1 < SW.g1) Gn = load_gate(cptr(d.segs) + gi + 1);
-                if (adj && G.slot >= 0) {
+                const GateOp G = o0;
+                const Coef8<R> c = cn;
+                o0 = o1;
+                if (gi + 2 < SW.g1) o1 = load_op(sg + gi + 2);
+                if (gi + 1 < SW.g1) cn = load_coef(mats + 2 * (uint64_t)o0.mat);
+                if (adj && gi_param(G.info)) {
                     double re = 0.0, im = 0.0;
-                    if (act) reg_inner(l, x, G.xl, G.zl, &re, &im);
+                    if (act) reg_inner(l, x, gi_xl(G.info), gi_zl(G.info), &re, &im);
                     re = wave_total63(re);
                     im = wave_total63(im);
                     // one wave adds into its own slot, in program order
@@ -435,9 +468,9 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                     ++p;
                 }
                 if (act) {
-                    CPtr<R> m = mats + 2 * G.mat;
-                    reg_apply(G, x, m);
-                    if (adj) reg_apply(G, l, m);
+                    CPtr<R> m = mats + 2 * (uint64_t)G.mat;
+                    reg_apply(G.info, x, c, m);
+                    if (adj) reg_apply(G.info, l, c, m);
                 }
             }
             if (act) {
