@@ -29,6 +29,7 @@ struct InstPlan {
     std::vector<std::vector<cplx>> fixed;  // fixed matrices (sorted-qubit order), per gate
     std::vector<int> sq0, sq1;             // sorted targets per gate
     std::vector<int> form;                 // BatchForm of each gate's matrix (all parameter values)
+    std::vector<uint32_t> neg;             // BF_SIGN: local indices of the -1 diagonal entries
     std::vector<uint32_t> xl, zl;          // local generator masks per gate
     std::vector<int> gen_sorted;           // generator letters in sorted local order
     std::vector<uint64_t> gx, gz;          // global generator masks per gate
@@ -404,6 +405,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         const size_t L = ip.gates.size();
         ip.fixed.resize(L);
         ip.form.assign(L, BF_GENERAL);
+        ip.neg.assign(L, 0);
         ip.sq0.resize(L);
         ip.sq1.resize(L);
         ip.xl.assign(L, 0);
@@ -458,14 +460,17 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 if (nx == 0 && ny == 0) ip.form[l] = BF_DIAG;
                 else if (ny % 2 == 1) ip.form[l] = BF_REAL;
             } else {
-                bool diag = true, real = true;
+                bool diag = true, real = true, sign = true;
                 for (int r = 0; r < D; ++r)
                     for (int c = 0; c < D; ++c) {
                         const cplx z = ip.fixed[l][(size_t)r * D + c];
                         if (r != c && z != cplx(0, 0)) diag = false;
                         if (z.imag() != 0.0) real = false;
+                        if (r == c && z != cplx(1, 0) && z != cplx(-1, 0)) sign = false;
                     }
-                ip.form[l] = diag ? BF_DIAG : real ? BF_REAL : BF_GENERAL;
+                ip.form[l] = diag ? (sign ? BF_SIGN : BF_DIAG) : real ? BF_REAL : BF_GENERAL;
+                for (int r = 0; r < D && ip.form[l] == BF_SIGN; ++r)
+                    if (ip.fixed[l][(size_t)r * D + r] == cplx(-1, 0)) ip.neg[l] |= 1u << r;
             }
             ip.mat_fwd[l] = mat_entries;
             mat_entries += (uint64_t)D * D;
@@ -480,7 +485,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         std::vector<char> gdiag(L, 0);
         for (size_t l = 0; l < L; ++l) {
             for (int a = 0; a < ip.gates[l].k; ++a) gmask[l] |= 1ull << ip.gates[l].qubits[a];
-            gdiag[l] = ip.form[l] == BF_DIAG;
+            gdiag[l] = ip.form[l] == BF_DIAG || ip.form[l] == BF_SIGN;
         }
         auto segment = [&](bool reverse) { return segment_gates(gmask, gdiag, ip.tb, reverse, batch_reorder()); };
         for (auto &sg : segment(false)) {
@@ -653,7 +658,9 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                             if ((ip.xl[l] >> bb) & 1u) xl |= 1u << sb;
                             if ((ip.zl[l] >> bb) & 1u) zl |= 1u << sb;
                         }
-                        sgt.info = seg_info(k, t0, t1, ip.form[l], xl, zl, sgt.slot >= 0);
+                        // sign pattern: gate-local index -> sweep bits t0 / t1 stay in
+                        // the same order (bit 0 <-> t0 < t1 <-> bit 1)
+                        sgt.info = seg_info(k, t0, t1, ip.form[l], xl, zl, sgt.slot >= 0, ip.neg[l]);
                         sgt.mat = (uint32_t)(op.kind == BK_FWD ? ip.mat_fwd[l] : ip.mat_adj[l]);
                         if (sgt.slot >= 0) ++nparam;
                         segs.push_back(sgt);

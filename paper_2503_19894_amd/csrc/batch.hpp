@@ -32,23 +32,26 @@ constexpr size_t kSegLdsExtra = 128 * sizeof(uint64_t) + (size_t)kSegMaxGates * 
 struct SegGate {            // one gate of a sweep, in sweep coordinates
     // packed: bit 0 k - 1; bits 1-2 t0 and 3-4 t1, the sweep bits (0..2) of
     // the sorted targets (t1 unused for k = 1); bits 5-6 the matrix form for
-    // every parameter value (BF_GENERAL, BF_DIAG or BF_REAL); bits 7-9 xl and
-    // 10-12 zl, the generator's x / z masks over the sweep bits (ADJ); bit 13
-    // set when the gate has a result slot
+    // every parameter value (BF_GENERAL, BF_DIAG, BF_REAL or BF_SIGN); bits 7-9
+    // xl and 10-12 zl, the generator's x / z masks over the sweep bits (ADJ);
+    // bit 13 set when the gate has a result slot; bits 14-17 (BF_SIGN) the
+    // local indices whose diagonal entry is -1
     uint32_t info;
     uint32_t mat;           // offset (complex entries) of U (FWD) or U^dag (ADJ): its 2^k x 2^k
                             // entries, or for a two-qubit diagonal form its diagonal first
     int slot;               // ADJ: result slot, or -1
     int pad;
 };
-inline uint32_t seg_info(int k, int t0, int t1, int form, uint32_t xl, uint32_t zl, bool param) {
+inline uint32_t seg_info(int k, int t0, int t1, int form, uint32_t xl, uint32_t zl, bool param, uint32_t neg) {
     return (uint32_t)(k - 1) | (uint32_t)t0 << 1 | (uint32_t)(t1 < 0 ? 0 : t1) << 3 | (uint32_t)form << 5 |
-           xl << 7 | zl << 10 | (uint32_t)param << 13;
+           xl << 7 | zl << 10 | (uint32_t)param << 13 | (neg & 15u) << 14;
 }
 
 // Matrix forms the register sweeps specialise (fewer multiplies): diagonal
 // (e.g. RZ, RZZ, CZ) and real (e.g. RY).
-enum BatchForm : int { BF_GENERAL = 0, BF_DIAG = 1, BF_REAL = 2 };
+// A fixed diagonal gate whose entries are all +1 or -1 (e.g. CZ) is a sign
+// pattern: BF_SIGN, its -1 entries in info bits 14-17, no matrix read.
+enum BatchForm : int { BF_GENERAL = 0, BF_DIAG = 1, BF_REAL = 2, BF_SIGN = 3 };
 
 struct SegSweep {           // consecutive gates of a segment on at most three tile bits
     int b[3];               // the sweep's tile bits, ascending

@@ -140,6 +140,20 @@ __device__ __forceinline__ void reg_diag(V *x, const M &m) {
     }
 }
 
+// Sign pattern on sweep bits (B0, B1; B1 < 0 for one qubit): x[j] = -x[j]
+// where the gate's diagonal entry for j's bits is -1 (`neg`, wave-uniform).
+template <int B0, int B1, typename V>
+__device__ __forceinline__ void reg_sign(V *x, uint32_t neg) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int loc = ((j >> B0) & 1) | (B1 < 0 ? 0 : ((j >> (B1 < 0 ? 0 : B1)) & 1) << 1);
+        if ((neg >> loc) & 1u) {
+            x[j].x = -x[j].x;
+            x[j].y = -x[j].y;
+        }
+    }
+}
+
 // Real matrix: only the real parts of the entries are read (two multiplies per entry).
 template <int B, typename V, typename M>
 __device__ __forceinline__ void reg_real1(V *x, const M &m) {
@@ -193,6 +207,22 @@ __device__ __forceinline__ bool gi_param(uint32_t i) { return (i >> 13) & 1u; }
 template <typename V, typename R>
 __device__ __forceinline__ void reg_apply(uint32_t info, V *x, const Coef8<R> &c, CPtr<R> m) {
     const int k = gi_k(info), t0 = gi_t0(info), t1 = gi_t1(info), form = gi_form(info);
+    if (form == BF_SIGN) {
+        const uint32_t neg = (info >> 14) & 15u;
+        if (k == 1) {
+            switch (t0) {
+                case 0: reg_sign<0, -1>(x, neg); break;
+                case 1: reg_sign<1, -1>(x, neg); break;
+                default: reg_sign<2, -1>(x, neg); break;
+            }
+        } else if (t0 == 0) {
+            if (t1 == 1) reg_sign<0, 1>(x, neg);
+            else reg_sign<0, 2>(x, neg);
+        } else {
+            reg_sign<1, 2>(x, neg);
+        }
+        return;
+    }
     if (form == BF_DIAG) {
         if (k == 1) {
             switch (t0) {
