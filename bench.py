@@ -72,8 +72,10 @@ def kernel_label(info, dtype_name):
         return f"k_direct<{d}, {r}, {ipt}, {nt}>"
     m3 = "true" if d >= cast.get_tuning("mfma_3m_min_d", dt) else "false"
     if kind == 4:
-        pre = "true" if cast.get_tuning("mfma_prefetch", dt) else "false"
-        return f"k_mfma_direct<{d}, {r}, {m3}, {pre}>"
+        pre = cast.get_tuning("mfma_prefetch", dt)
+        if pre >= 2 and d < 6:
+            return f"k_mfma_direct_db<{d}, {r}, {m3}>"
+        return f"k_mfma_direct<{d}, {r}, {m3}, {'true' if pre else 'false'}>"
     if kind == 5:
         return f"k_mfma_tile<{d}, {r}, {m3}>"
     two = "true" if kind == 2 else "false"

@@ -45,7 +45,7 @@ KNOB_CHOICES = [
     ("diag_run_unroll", [1, 2, 4]),
     ("diag_run_grid", [1 << 12, 1 << 16, 1 << 20]),
     ("diag_run_lds", [0, 1]),
-    ("mfma_prefetch", [0, 1]),
+    ("mfma_prefetch", [0, 1, 2]),
     ("diag_run_reuse", [0, 2, 4, 6]),
     ("direct_rot", [0, 1, 2, 3]),
 ]

@@ -524,7 +524,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "diag_run_unroll") { *lo = 1; *hi = 4; return &t.diag_run_unroll[i]; }
     if (key == "diag_run_grid") { *lo = 256; return &t.diag_run_grid[i]; }
     if (key == "diag_run_lds") { *hi = 1; return &t.diag_run_lds[i]; }
-    if (key == "mfma_prefetch") { *hi = 1; return &t.mfma_prefetch[i]; }
+    if (key == "mfma_prefetch") { *hi = 2; return &t.mfma_prefetch[i]; }
     if (key == "diag_spread") { *hi = 1; return &t.diag_spread[i]; }
     if (key == "diag_run_reuse") { *hi = 12; return &t.diag_run_reuse[i]; }
     if (key == "direct_rot") { *hi = 16; return &t.direct_rot[i]; }

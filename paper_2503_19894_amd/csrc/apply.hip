@@ -568,6 +568,65 @@ __device__ __forceinline__ void mfma_unit(const typename Amp<R>::T *mt_blk, Load
     }
 }
 
+// The product of one unit from inputs already in registers: xs[s] is this
+// lane's k-row 4s + lane / 16 of the unit's 16 groups.
+template <int D, typename R, bool M3, typename Store>
+__device__ __forceinline__ void mfma_core(const typename Amp<R>::T *mt_blk, const typename Amp<R>::T *xs, Store store) {
+    using V = typename Amp<R>::T;
+    using M = Mfma<R>;
+    constexpr int N = 1 << D, T = N / 16;
+    const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+    typename M::acc cr[T], ci[T], cs[M3 ? T : 1];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            cr[t][v] = ci[t][v] = 0;
+            if (M3) cs[t][v] = 0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < N / 4; ++s) {
+        const int c = 4 * s + kk;
+        const V x = xs[s];
+        const V *col = mt_blk + c * N + j;
+        if (M3) {
+            const R xsum = x.x + x.y;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const V u = col[16 * t];
+                cr[t] = M::mma(u.x, x.x, cr[t]);
+                ci[t] = M::mma(u.y, x.y, ci[t]);
+                cs[t] = M::mma(u.x + u.y, xsum, cs[t]);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const V u = col[16 * t];
+                cr[t] = M::mma(u.x, x.x, cr[t]);
+                cr[t] = M::mma(-u.y, x.y, cr[t]);
+                ci[t] = M::mma(u.x, x.y, ci[t]);
+                ci[t] = M::mma(u.y, x.x, ci[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            V y;
+            if (M3) {
+                y.x = cr[t][v] - ci[t][v];
+                y.y = cs[t][v] - cr[t][v] - ci[t][v];
+            } else {
+                y.x = cr[t][v];
+                y.y = ci[t][v];
+            }
+            store(16 * t + M::row(lane, v), y);
+        }
+    }
+}
+
 template <int D>
 __device__ __forceinline__ uint64_t off_of(const uint64_t *off, int c) {
     uint64_t o = 0;
@@ -603,6 +662,64 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
         auto ld = [&](int c) { return psi[base ^ off_of<D>(a.off, c)]; };
         auto st = [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; };
         mfma_unit<D, R, M3, decltype(ld), decltype(st), PRE>(mt + (size_t)bs * N * N, ld, st);
+    }
+}
+
+// k_mfma_direct with the inputs of a wave's next unit requested before the
+// matrix-core products of the current one, so a wave's memory traffic
+// overlaps its own products instead of alternating with them (the products
+// of a 32-dimensional block take about as long as its loads).
+template <int D, typename R, bool M3>
+__global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, const R *__restrict__ mat,
+                                                        PassArgs a) {
+    using V = typename Amp<R>::T;
+    constexpr int N = 1 << D;
+    extern __shared__ uint4 lds_raw[];
+    V *mt = reinterpret_cast<V *>(lds_raw);
+    V *psi = reinterpret_cast<V *>(psi_r);
+    stage_blocks<D>(mt, mat, a.nblk);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15, kk = lane >> 4;
+    const uint64_t units = (a.ngroups >> 4) * a.nblk;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    // group base and block slot of unit u
+    auto locate = [&](uint64_t u, uint32_t &bs) {
+        const uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        const uint32_t gu = uu / a.nblk;
+        bs = uu - gu * a.nblk;
+        const uint64_t g = (uint64_t)gu * 16 + j;
+        const uint32_t bid = a.blk[bs];
+        uint64_t base = deposit(g, a.lowmask, a.k);
+        for (int q = 0; q < a.k - D; ++q)
+            if ((bid >> q) & 1u) base ^= a.off[D + q];
+        return base;
+    };
+    uint64_t u = (uint64_t)blockIdx.x * 4 + wave;
+    if (u >= units) return;
+    uint32_t bs;
+    uint64_t base = locate(u, bs);
+    V xs[N / 4];
+#pragma unroll
+    for (int s = 0; s < N / 4; ++s) xs[s] = psi[base ^ off_of<D>(a.off, 4 * s + kk)];
+    for (;;) {
+        const uint64_t un = u + stride;
+        const bool more = un < units;
+        uint32_t bsn = 0;
+        uint64_t basen = 0;
+        V xn[N / 4];
+        if (more) {
+            basen = locate(un, bsn);
+#pragma unroll
+            for (int s = 0; s < N / 4; ++s) xn[s] = psi[basen ^ off_of<D>(a.off, 4 * s + kk)];
+        }
+        auto st = [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; };
+        mfma_core<D, R, M3>(mt + (size_t)bs * N * N, xs, st);
+        if (!more) break;
+        u = un;
+        bs = bsn;
+        base = basen;
+#pragma unroll
+        for (int s = 0; s < N / 4; ++s) xs[s] = xn[s];
     }
 }
 
@@ -847,8 +964,13 @@ bool mfma_fits(int n, cast_dtype dt, const PassPlan &p) {
 }
 
 template <typename R>
-static hipError_t launch_mfma(int D, bool tile, bool m3, bool pre, R *psi, const R *m, const PassArgs &a, int grid,
+static hipError_t launch_mfma(int D, bool tile, bool m3, int prefetch, R *psi, const R *m, const PassArgs &a, int grid,
                               size_t lds, hipStream_t s) {
+    // prefetch 1: a unit's inputs all requested before its products; 2: the
+    // next unit's inputs requested before the current unit's products
+    // (the 64-dimensional blocks keep 1: two units of inputs would take
+    // every register and leave one wave per SIMD)
+    const bool pre2 = prefetch >= 2 && D < 6, pre = prefetch == 1 || (prefetch >= 2 && !pre2);
 #define CAST_MFMA_K(KERN, ...)                                                                           \
     {                                                                                                    \
         static bool set = false;                                                                         \
@@ -864,6 +986,8 @@ static hipError_t launch_mfma(int D, bool tile, bool m3, bool pre, R *psi, const
     case DD:                                                                                             \
         if (tile) {                                                                                      \
             if (m3) CAST_MFMA_K(k_mfma_tile, DD, R, true) else CAST_MFMA_K(k_mfma_tile, DD, R, false)   \
+        } else if (pre2) {                                                                               \
+            if (m3) CAST_MFMA_K(k_mfma_direct_db, DD, R, true) else CAST_MFMA_K(k_mfma_direct_db, DD, R, false) \
         } else if (pre) {                                                                                \
             if (m3) CAST_MFMA_K(k_mfma_direct, DD, R, true, true)                                       \
             else CAST_MFMA_K(k_mfma_direct, DD, R, false, true)                                          \
@@ -937,11 +1061,11 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             lds += ((size_t)1 << tb) * amp_bytes(dt);
         }
         if (dt == CAST_C128)
-            e = launch_mfma<double>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt] != 0, (double *)psi,
+            e = launch_mfma<double>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt], (double *)psi,
                                     (const double *)dmat, a,
                                     (int)grid, lds, stream);
         else
-            e = launch_mfma<float>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt] != 0, (float *)psi,
+            e = launch_mfma<float>(D, kind == 5, D >= tu.mfma_3m_min_d[dt], tu.mfma_prefetch[dt], (float *)psi,
                                    (const float *)dmat, a,
                                    (int)grid, lds, stream);
     } else if (kind == 3) {

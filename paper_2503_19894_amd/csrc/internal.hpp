@@ -93,7 +93,8 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int diag_run_unroll[3] = {0, 2, 4};
     int diag_run_grid[3] = {0, 1 << 16, 1 << 16};
     int diag_run_lds[3] = {0, 1, 1};     // diagonal runs: phase tables in LDS (1) or read through L1 (0)
-    int mfma_prefetch[3] = {0, 1, 1};    // matrix-core direct kernel: all of a unit's loads before its products
+    int mfma_prefetch[3] = {0, 1, 1};    // matrix-core direct kernel: 1 all of a unit's loads before its
+                                         // products, 2 also the next unit's (0: one k-step ahead)
     int diag_spread[3] = {0, 1, 1};      // diagonal kernels: tiles dealt to XCDs by a digit hash (else round-robin)
     // diagonal runs: log2 of the free-bit patterns one work unit streams with
     // one phase lookup per lane (phase reuse; 0: the tiled run kernel)

@@ -36,13 +36,14 @@ def test_dense_haar_22_vs_oracle(dtype, tol):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-5)], ids=["c128", "c64"])
 @pytest.mark.parametrize("m3_min_d", [4, 7], ids=["3m_from_d4", "4m_only"])
-@pytest.mark.parametrize("prefetch", [0, 1], ids=["stepwise_loads", "prefetch"])
+@pytest.mark.parametrize("prefetch", [0, 1, 2], ids=["stepwise_loads", "prefetch", "next_unit_prefetch"])
 def test_dense_mfma_product_forms(dtype, tol, m3_min_d, prefetch):
     """The matrix-core passes with the three-multiplication complex product
     at every block size (d >= 4) and with the four-product form only, on
     direct and LDS-tile placements (the 4-qubit gate on 0, 2, 5, 9 goes to
     the tile kernel), with the direct kernel's inputs loaded one k-step
-    ahead or all before the first product, against the oracle."""
+    ahead, all before the first product, or the next unit's before this
+    unit's products, against the oracle."""
     n = 16
     gates = dense_haar_layers(n, depth=2, seed=3)
     gates.append(Gate("unitary", (0, 2, 5, 9), matrix=_haar(16, 5)))
