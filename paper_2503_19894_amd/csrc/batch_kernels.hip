@@ -367,21 +367,30 @@ __device__ __forceinline__ uint32_t bat(uint32_t e) { return (bswz(e >> S) << S)
 // per-gate, per-wave partial sums of the segment's inner products (at most
 // kSegMaxGates gates), then the psi tile and (ADJ only) the lambda tile, 2^tb
 // amplitudes each, swizzled as above.  A forward step's launch carries one
-// tile's LDS, so more of its workgroups share a compute unit.
+// tile's LDS, so more of its workgroups share a compute unit.  `pair` (FWD in
+// the persistent launch, whose workgroups hold two tiles of LDS anyway):
+// tiles w and w + 1 of psi go through the segment together in the two tile
+// slots, the second one taking the lambda tile's place.
 template <typename R>
 __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst &in, uint32_t w, double *red,
-                         typename BAmp<R>::T *lds) {
+                         typename BAmp<R>::T *lds, bool pair) {
     using V = typename BAmp<R>::T;
     constexpr int S = sizeof(V) == 16 ? 0 : 1;      // log2(amplitudes per 16-byte chunk)
     const bool adj = rec->kind == BK_ADJ;
+    const bool two = adj || pair;                    // a second tile in the lambda slot
     const uint32_t T = 1u << rec->tb;
     uint64_t *hid = reinterpret_cast<uint64_t *>(lds);            // [2][64]
     double *gsum = reinterpret_cast<double *>(hid + 128);         // [kSegMaxGates][4 waves][2]
     V *tp = reinterpret_cast<V *>(reinterpret_cast<char *>(lds) + kSegLdsExtra), *tl = tp + T;
     V *psi = reinterpret_cast<V *>(in.psi);
     V *lam = reinterpret_cast<V *>(in.lam);
-    uint64_t tbase = (uint64_t)w << rec->W;
-    for (int j = 0; j < rec->khi; ++j) tbase = ins0(tbase, rec->qhi[j]);
+    uint64_t tbase = (uint64_t)w << rec->W, tbase2 = (uint64_t)(w + 1) << rec->W;
+    for (int j = 0; j < rec->khi; ++j) tbase = ins0(tbase, rec->qhi[j]), tbase2 = ins0(tbase2, rec->qhi[j]);
+    // the second tile: lambda's tile w, or psi's tile w + 1 (its amplitude
+    // index differs from tile w's by the XOR of the two tile bases, which
+    // lie above the tile's low window)
+    V *sec = pair ? psi : lam;
+    const uint64_t dsec = pair ? (tbase ^ tbase2) : 0;
     for (int i = threadIdx.x; i < kSegMaxGates * 4 * 2; i += blockDim.x) gsum[i] = 0.0;
     if (threadIdx.x < 128) {
         const uint32_t h = threadIdx.x >> 6, r = threadIdx.x & 63;
@@ -408,7 +417,7 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
         constexpr int DEPTH = 8;
         typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
         nu4 *t16p = reinterpret_cast<nu4 *>(tp), *t16l = reinterpret_cast<nu4 *>(tl);
-        const nu4 *p16 = reinterpret_cast<const nu4 *>(psi), *l16 = reinterpret_cast<const nu4 *>(lam);
+        const nu4 *p16 = reinterpret_cast<const nu4 *>(psi), *l16 = reinterpret_cast<const nu4 *>(sec);
         for (uint32_t c0 = threadIdx.x; c0 < nchunk; c0 += DEPTH * blockDim.x) {
             nu4 bp[DEPTH], bl[DEPTH];
 #pragma unroll
@@ -417,7 +426,7 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                 if (c < nchunk) {
                     const uint64_t x = addr(c << S) >> S;
                     bp[u] = p16[x];
-                    if (adj) bl[u] = l16[x];
+                    if (two) bl[u] = l16[x ^ (dsec >> S)];
                 }
             }
 #pragma unroll
@@ -425,7 +434,7 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                 const uint32_t c = c0 + u * blockDim.x;
                 if (c < nchunk) {
                     t16p[bswz(c)] = bp[u];
-                    if (adj) t16l[bswz(c)] = bl[u];
+                    if (two) t16l[bswz(c)] = bl[u];
                 }
             }
         }
@@ -433,7 +442,7 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
         for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
             const uint64_t x = addr(e);
             tp[bat<S>(e)] = psi[x];
-            if (adj) tl[bat<S>(e)] = lam[x];
+            if (two) tl[bat<S>(e)] = sec[x ^ dsec];
         }
     }
     __syncthreads();
@@ -466,7 +475,7 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                 bb = bat<S>(ins0_32(ins0_32(ins0_32(g, SW.b[0]), SW.b[1]), SW.b[2])) * (uint32_t)sizeof(V);
 #pragma unroll
                 for (int j = 0; j < 8; ++j) x[j] = *reinterpret_cast<const V *>(tpb + (bb ^ so[j]));
-                if (adj) {
+                if (two) {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) l[j] = *reinterpret_cast<const V *>(tlb + (bb ^ so[j]));
                 }
@@ -500,13 +509,13 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
                 if (act) {
                     CPtr<R> m = mats + 2 * (uint64_t)G.mat;
                     reg_apply(G.info, x, c, m);
-                    if (adj) reg_apply(G.info, l, c, m);
+                    if (two) reg_apply(G.info, l, c, m);
                 }
             }
             if (act) {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) *reinterpret_cast<V *>(tpb + (bb ^ so[j])) = x[j];
-                if (adj) {
+                if (two) {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) *reinterpret_cast<V *>(tlb + (bb ^ so[j])) = l[j];
                 }
@@ -536,17 +545,17 @@ __device__ void seg_item(const BatchDev &d, CPtr<BatchRec> rec, const BatchInst 
     }
     if (chunked) {
         const uint4 *t16p = reinterpret_cast<const uint4 *>(tp), *t16l = reinterpret_cast<const uint4 *>(tl);
-        uint4 *p16 = reinterpret_cast<uint4 *>(psi), *l16 = reinterpret_cast<uint4 *>(lam);
+        uint4 *p16 = reinterpret_cast<uint4 *>(psi), *l16 = reinterpret_cast<uint4 *>(sec);
         for (uint32_t c = threadIdx.x; c < nchunk; c += blockDim.x) {
             const uint64_t x = addr(c << S) >> S;
             p16[x] = t16p[bswz(c)];
-            if (adj) l16[x] = t16l[bswz(c)];
+            if (two) l16[x ^ (dsec >> S)] = t16l[bswz(c)];
         }
     } else {
         for (uint32_t e = threadIdx.x; e < T; e += blockDim.x) {
             const uint64_t x = addr(e);
             psi[x] = tp[bat<S>(e)];
-            if (adj) lam[x] = tl[bat<S>(e)];
+            if (two) sec[x ^ dsec] = tl[bat<S>(e)];
         }
     }
     __syncthreads();   // the LDS tables and tiles are reused by the next item
@@ -591,12 +600,13 @@ __device__ void hpsi_range(const BatchInst &in, const PauliSumGroup *tg, const P
 }
 
 // One work item: item w of record rec.
+// One work item: item w of record rec (pair: items w and w + 1 of a FWD record).
 template <typename R>
-__device__ void run_item(const BatchDev &d, CPtr<BatchRec> rec, uint32_t w, double *red) {
+__device__ void run_item(const BatchDev &d, CPtr<BatchRec> rec, uint32_t w, double *red, bool pair = false) {
     using V = typename BAmp<R>::T;
     const BatchInst in = load_inst(cptr(d.insts) + rec->inst);
     if (rec->kind != BK_HPSI) {
-        seg_item<R>(d, rec, in, w, red, reinterpret_cast<V *>(batch_lds));
+        seg_item<R>(d, rec, in, w, red, reinterpret_cast<V *>(batch_lds), pair);
         return;
     }
     double re = 0.0, im = 0.0;
@@ -707,14 +717,19 @@ __global__ void __launch_bounds__(256) k_batch_persistent(BatchDev d, uint64_t t
             }
             __syncthreads();
             if (__builtin_amdgcn_readfirstlane(stop_sh)) break;
-            run_item<R>(d, rec, (uint32_t)(x - rec->item0), red);
+            // two forward items of one record claimed together run as a pair
+            // (same gates, both tile slots of this workgroup's LDS)
+            const uint32_t w = (uint32_t)(x - rec->item0);
+            const bool pair = rec->kind == BK_FWD && item + 1 < end && w + 1 < rec->wgs;
+            run_item<R>(d, rec, w, red, pair);
             // the barrier makes every wave's stores visible to the workgroup;
             // thread 0's agent-scope release later publishes them device-wide
             __syncthreads();
             if (threadIdx.x == 0) {
                 pend_inst = rec->inst;
-                ++pend;
+                pend += pair ? 2 : 1;
             }
+            if (pair) ++item;
         }
         if (threadIdx.x == 0 && pend) {
             __hip_atomic_fetch_add(&counters[2 + pend_inst], pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
