@@ -281,8 +281,41 @@ __device__ __forceinline__ void reg_inner_x(const V *l, const V *x, uint32_t zl,
     }
 }
 
+// The same sum with the generator's x and z masks known at compile time:
+// signs and partner registers are fixed, so it is straight-line adds and
+// subtracts.
+template <int X, int Z, typename V>
+__device__ __forceinline__ void reg_inner_xz(const V *l, const V *x, double *re, double *im) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const V a = l[j ^ X];
+        const double pr = (double)a.x * x[j].x + (double)a.y * x[j].y;
+        const double pi = (double)a.x * x[j].y - (double)a.y * x[j].x;
+        if (__builtin_popcount(Z & j) & 1) {
+            *re -= pr;
+            *im -= pi;
+        } else {
+            *re += pr;
+            *im += pi;
+        }
+    }
+}
+
 template <typename V>
 __device__ __forceinline__ void reg_inner(const V *l, const V *x, uint32_t xl, uint32_t zl, double *re, double *im) {
+    // one-qubit generators on a sweep bit b: Z (0, b), X (b, 0), Y (b, b)
+    switch (xl * 8 + zl) {
+        case 0 * 8 + 1: reg_inner_xz<0, 1>(l, x, re, im); return;
+        case 0 * 8 + 2: reg_inner_xz<0, 2>(l, x, re, im); return;
+        case 0 * 8 + 4: reg_inner_xz<0, 4>(l, x, re, im); return;
+        case 1 * 8 + 0: reg_inner_xz<1, 0>(l, x, re, im); return;
+        case 2 * 8 + 0: reg_inner_xz<2, 0>(l, x, re, im); return;
+        case 4 * 8 + 0: reg_inner_xz<4, 0>(l, x, re, im); return;
+        case 1 * 8 + 1: reg_inner_xz<1, 1>(l, x, re, im); return;
+        case 2 * 8 + 2: reg_inner_xz<2, 2>(l, x, re, im); return;
+        case 4 * 8 + 4: reg_inner_xz<4, 4>(l, x, re, im); return;
+        default: break;
+    }
     switch (xl) {
         case 0: reg_inner_x<0>(l, x, zl, re, im); break;
         case 1: reg_inner_x<1>(l, x, zl, re, im); break;
