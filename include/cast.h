@@ -223,7 +223,9 @@ cast_status circuit_set_pass_shape(cast_fused *f, int n, cast_dtype dt, size_t i
  * than 1 % faster.  The passes are applied to sv in place, so its amplitudes
  * change (they stay normalised: every pass is unitary).  *before_ms and
  * *after_ms (may be NULL) receive the summed minimum times of the direct
- * passes with the knobs' shapes and with the chosen ones.  Synchronous. */
+ * passes with the knobs' shapes and with the chosen ones.  Synchronous.  The
+ * shapes live in the list: do not tune a list while another thread applies
+ * it (the same holds for circuit_set_pass_shape). */
 cast_status circuit_tune(cast_sv *sv, cast_fused *f, int reps, double *before_ms, double *after_ms);
 
 /* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct

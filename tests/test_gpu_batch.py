@@ -87,6 +87,31 @@ def test_batch_larger_states_cross_workgroups():
             assert np.max(np.abs(g[i] - gw)) <= 1e-10
 
 
+def test_persistent_pairs_bitwise_and_vs_oracle():
+    """Paired forward items of the persistent launch (two tiles of one record
+    in one workgroup), with records that start at odd item offsets (a
+    one-item instance before each large one) and claims that end between
+    the two items of a would-be pair: bitwise equal to the per-step launch
+    (which never pairs) and within the bar of the oracle."""
+    ns = [4, 14, 5, 14]
+    obs = [PauliTerm(1.0, ((0, "Z"),)), PauliTerm(0.5, ((1, "X"),))]
+    circs = [tfim_trotter(n, steps=3, dt=0.07) for n in ns]
+    fields = [tfim_fields(n, seed=20 + i) for i, n in enumerate(ns)]
+    outs = {}
+    for mode in (cast.BATCH_STEPS, cast.BATCH_PERSISTENT_GRAPH):
+        b = cast.Batch(circs, ns, ns, [obs] * len(ns), init=["plus"] * len(ns), mode=mode)
+        outs[mode] = b.run(fields)
+    e0, g0 = outs[cast.BATCH_STEPS]
+    e1, g1 = outs[cast.BATCH_PERSISTENT_GRAPH]
+    assert np.array_equal(e0, e1)
+    assert all(np.array_equal(x, y) for x, y in zip(g0, g1))
+    for i, n in enumerate(ns):
+        psi0 = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+        ew, gw = oracle.adjoint_grad(n, circs[i], fields[i], obs, psi0)
+        assert abs(e1[i] - ew) <= 1e-10
+        assert np.max(np.abs(g1[i] - gw)) <= 1e-10
+
+
 def test_init_state_copy():
     n = 7
     gates, P, th, H = vqa_case(n, layers=1, sets=2)
