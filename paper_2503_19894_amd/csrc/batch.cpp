@@ -93,10 +93,12 @@ static void sorted_matrix(int k, const int *qubits, const std::vector<cplx> &m, 
 }
 
 // Writes a gate's matrix entry into the pinned table in the state dtype: its
-// 2^k x 2^k entries row-major (dagger: those of the adjoint), or for a
-// two-qubit diagonal form its four diagonal entries first, the layout the
-// batched kernels read.
-static void put_matrix(cast_batch *b, uint64_t off, const cplx *m, bool dagger, int k, bool diag_form) {
+// 2^k x 2^k entries row-major (dagger: those of the adjoint), or compactly
+// for the forms the batched kernels read so: a two-qubit diagonal its four
+// diagonal entries; a Pauli pair (BF_PAULI, masks xm / zm) a and b of
+// y_r = a x_r + b (-1)^{popc(zm & (r ^ xm))} x_{r ^ xm}.
+static void put_matrix(cast_batch *b, uint64_t off, const cplx *m, bool dagger, int k, int form, uint32_t xm,
+                       uint32_t zm) {
     const int D = 1 << k;
     auto put = [&](uint64_t e, cplx z) {
         if (b->dt == CAST_C128) {
@@ -107,18 +109,57 @@ static void put_matrix(cast_batch *b, uint64_t off, const cplx *m, bool dagger, 
             ((float *)b->h_mats)[2 * e + 1] = (float)z.imag();
         }
     };
-    if (diag_form && k == 2) {
-        for (int r = 0; r < D; ++r) put(off + r, dagger ? std::conj(m[r * D + r]) : m[r * D + r]);
+    auto at = [&](int r, int c) { return dagger ? std::conj(m[(size_t)c * D + r]) : m[(size_t)r * D + c]; };
+    if (k == 2 && (form == BF_DIAG || form == BF_PAULI)) {
+        if (form == BF_DIAG) {
+            for (int r = 0; r < D; ++r) put(off + r, at(r, r));
+        } else {
+            put(off, at(0, 0));
+            put(off + 1, at(0, (int)xm) * ((__builtin_popcount(zm & xm) & 1) ? -1.0 : 1.0));
+            for (int e = 2; e < D; ++e) put(off + e, 0.0);
+        }
         for (int e = D; e < D * D; ++e) put(off + e, 0.0);
         return;
     }
     for (int r = 0; r < D; ++r)
-        for (int c = 0; c < D; ++c) put(off + (uint64_t)r * D + c, dagger ? std::conj(m[(size_t)c * D + r]) : m[(size_t)r * D + c]);
+        for (int c = 0; c < D; ++c) put(off + (uint64_t)r * D + c, at(r, c));
+}
+
+// Whether a two-qubit matrix is a I + b P for one Pauli string P that flips
+// bits: nonzeros only on the diagonal (all equal) and at (r, r ^ x) for one
+// x != 0, with the off-diagonal signs those of a Z mask z (the i^{|x & z|}
+// of the Y letters folds into b).  On success, *xm and *zm (local bits).
+static bool pauli_pair(const std::vector<cplx> &m, uint32_t *xm, uint32_t *zm) {
+    const int D = 4;
+    for (uint32_t x = 1; x < (uint32_t)D; ++x) {
+        bool ok = true;
+        for (int r = 0; r < D && ok; ++r)
+            for (int c = 0; c < D && ok; ++c)
+                if (c != r && c != (int)(r ^ x) && m[(size_t)r * D + c] != cplx(0, 0)) ok = false;
+        for (int r = 1; r < D && ok; ++r)
+            if (m[(size_t)r * D + r] != m[0]) ok = false;
+        if (!ok) continue;
+        for (uint32_t z = 0; z < (uint32_t)D; ++z) {
+            const cplx b0 = m[x] * ((__builtin_popcount(z & x) & 1) ? -1.0 : 1.0);
+            bool good = true;
+            for (int r = 1; r < D && good; ++r) {
+                const cplx br = m[(size_t)r * D + (r ^ x)] * ((__builtin_popcount(z & (r ^ x)) & 1) ? -1.0 : 1.0);
+                if (std::abs(br - b0) > 1e-15 * (1.0 + std::abs(b0))) good = false;
+            }
+            if (good) {
+                *xm = x;
+                *zm = z;
+                return true;
+            }
+        }
+    }
+    return false;
 }
 
 // exp(-i a P / 2) = cos(a/2) I - i sin(a/2) P with P a Pauli string (2-bit
 // letters in local bit order): P has one nonzero per row, at column r ^ x.
-static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double angle, bool dagger, bool diag_form) {
+static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double angle, bool dagger, int form,
+                          uint32_t xm, uint32_t zm) {
     const int D = 1 << k;
     const double c = std::cos(angle / 2), s = std::sin(angle / 2) * (dagger ? -1.0 : 1.0);
     uint32_t x = 0;
@@ -140,7 +181,7 @@ static void bind_rotation(cast_batch *b, uint64_t off, int k, int gen, double an
         m[r * D + (r ^ (int)x)] += cplx(0, -1) * s * p;  // dagger: conj of a Hermitian P's coefficient
     }
     // U^dag = cos I + i sin P; the loop above used -s for it, and P is Hermitian
-    put_matrix(b, off, m, false, k, diag_form);
+    put_matrix(b, off, m, false, k, form, xm, zm);
 }
 
 static cast_status queue_program(cast_batch *b) {
@@ -459,6 +500,7 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 }
                 if (nx == 0 && ny == 0) ip.form[l] = BF_DIAG;
                 else if (ny % 2 == 1) ip.form[l] = BF_REAL;
+                else if (g.k == 2) ip.form[l] = BF_PAULI;   // masks: the generator's
             } else {
                 bool diag = true, real = true, sign = true;
                 for (int r = 0; r < D; ++r)
@@ -471,6 +513,12 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
                 ip.form[l] = diag ? (sign ? BF_SIGN : BF_DIAG) : real ? BF_REAL : BF_GENERAL;
                 for (int r = 0; r < D && ip.form[l] == BF_SIGN; ++r)
                     if (ip.fixed[l][(size_t)r * D + r] == cplx(-1, 0)) ip.neg[l] |= 1u << r;
+                uint32_t xm, zm;
+                if (ip.form[l] == BF_GENERAL && g.k == 2 && pauli_pair(ip.fixed[l], &xm, &zm)) {
+                    ip.form[l] = BF_PAULI;
+                    ip.xl[l] = xm;   // a fixed gate has no generator: its Pauli pair's masks
+                    ip.zl[l] = zm;
+                }
             }
             ip.mat_fwd[l] = mat_entries;
             mat_entries += (uint64_t)D * D;
@@ -733,8 +781,8 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
         return bail(fail(CAST_ENOMEM, "pinned result buffer"));
     for (auto &ip : b->inst)
         for (size_t l = 0; l < ip.gates.size(); ++l) {
-            put_matrix(b, ip.mat_fwd[l], ip.fixed[l].data(), false, ip.gates[l].k, ip.form[l] == BF_DIAG);
-            put_matrix(b, ip.mat_adj[l], ip.fixed[l].data(), true, ip.gates[l].k, ip.form[l] == BF_DIAG);
+            put_matrix(b, ip.mat_fwd[l], ip.fixed[l].data(), false, ip.gates[l].k, ip.form[l], ip.xl[l], ip.zl[l]);
+            put_matrix(b, ip.mat_adj[l], ip.fixed[l].data(), true, ip.gates[l].k, ip.form[l], ip.xl[l], ip.zl[l]);
         }
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(CAST_EHIP, "hipStreamCreate failed"));
@@ -795,8 +843,8 @@ cast_status batch_run(cast_batch *b, const double *const *theta, double *energie
             const cast_gate &g = ip.gates[l];
             if (g.param_id < 0) continue;
             const double a = g.param_coeff * theta[i][g.param_id];
-            bind_rotation(b, ip.mat_fwd[l], g.k, ip.gen_sorted[l], a, false, ip.form[l] == BF_DIAG);
-            bind_rotation(b, ip.mat_adj[l], g.k, ip.gen_sorted[l], a, true, ip.form[l] == BF_DIAG);
+            bind_rotation(b, ip.mat_fwd[l], g.k, ip.gen_sorted[l], a, false, ip.form[l], ip.xl[l], ip.zl[l]);
+            bind_rotation(b, ip.mat_adj[l], g.k, ip.gen_sorted[l], a, true, ip.form[l], ip.xl[l], ip.zl[l]);
         }
     }
     if (b->mode >= 1) {

@@ -31,11 +31,11 @@ constexpr size_t kSegLdsExtra = 128 * sizeof(uint64_t) + (size_t)kSegMaxGates * 
 
 struct SegGate {            // one gate of a sweep, in sweep coordinates
     // packed: bit 0 k - 1; bits 1-2 t0 and 3-4 t1, the sweep bits (0..2) of
-    // the sorted targets (t1 unused for k = 1); bits 5-6 the matrix form for
-    // every parameter value (BF_GENERAL, BF_DIAG, BF_REAL or BF_SIGN); bits 7-9
-    // xl and 10-12 zl, the generator's x / z masks over the sweep bits (ADJ);
-    // bit 13 set when the gate has a result slot; bits 14-17 (BF_SIGN) the
-    // local indices whose diagonal entry is -1
+    // the sorted targets (t1 unused for k = 1); bits 5-7 the matrix form for
+    // every parameter value (BatchForm); bits 8-10 xl and 11-13 zl, the x / z
+    // masks over the sweep bits of the generator (ADJ inner products) or of
+    // a BF_PAULI gate's Pauli string; bit 14 set when the gate has a result
+    // slot; bits 15-18 (BF_SIGN) the local indices whose diagonal entry is -1
     uint32_t info;
     uint32_t mat;           // offset (complex entries) of U (FWD) or U^dag (ADJ): its 2^k x 2^k
                             // entries, or for a two-qubit diagonal form its diagonal first
@@ -44,14 +44,18 @@ struct SegGate {            // one gate of a sweep, in sweep coordinates
 };
 inline uint32_t seg_info(int k, int t0, int t1, int form, uint32_t xl, uint32_t zl, bool param, uint32_t neg) {
     return (uint32_t)(k - 1) | (uint32_t)t0 << 1 | (uint32_t)(t1 < 0 ? 0 : t1) << 3 | (uint32_t)form << 5 |
-           xl << 7 | zl << 10 | (uint32_t)param << 13 | (neg & 15u) << 14;
+           xl << 8 | zl << 11 | (uint32_t)param << 14 | (neg & 15u) << 15;
 }
 
 // Matrix forms the register sweeps specialise (fewer multiplies): diagonal
 // (e.g. RZ, RZZ, CZ) and real (e.g. RY).
 // A fixed diagonal gate whose entries are all +1 or -1 (e.g. CZ) is a sign
 // pattern: BF_SIGN, its -1 entries in info bits 14-17, no matrix read.
-enum BatchForm : int { BF_GENERAL = 0, BF_DIAG = 1, BF_REAL = 2, BF_SIGN = 3 };
+// A two-qubit gate a I + b' P with P one Pauli string that flips bits (e.g.
+// RXX, RYY, or a fixed XX coupling) is BF_PAULI: y_r = a x_r + b s(r) x_{r^xm}
+// with s(r) = (-1)^{popc(zm & (r ^ xm))}, the masks in the record's xl / zl
+// fields and (a, b) the first two complex entries of its matrix slot.
+enum BatchForm : int { BF_GENERAL = 0, BF_DIAG = 1, BF_REAL = 2, BF_SIGN = 3, BF_PAULI = 4 };
 
 struct SegSweep {           // consecutive gates of a segment on at most three tile bits
     int b[3];               // the sweep's tile bits, ascending

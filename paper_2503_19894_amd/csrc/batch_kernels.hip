@@ -154,6 +154,31 @@ __device__ __forceinline__ void reg_sign(V *x, uint32_t neg) {
     }
 }
 
+// Pauli pair y_j = a x_j + b s(j) x_{j^X}, s(j) = (-1)^{popc(zl & (j ^ X))}
+// (X over the sweep bits, compile time; zl wave-uniform): two complex
+// products per amplitude where the dense two-qubit form takes four.
+template <int X, typename V, typename R>
+__device__ __forceinline__ void reg_pauli(V *x, const Coef8<R> &c, uint32_t zl) {
+    const R ar = c[0], ai = c[1], br = c[2], bi = c[3];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = j ^ X;
+        if (k < j) continue;   // each pair once
+        const V xj = x[j], xk = x[k];
+        V pj, pk;              // b x_k, b x_j
+        pj.x = br * xk.x - bi * xk.y;
+        pj.y = br * xk.y + bi * xk.x;
+        pk.x = br * xj.x - bi * xj.y;
+        pk.y = br * xj.y + bi * xj.x;
+        if (__popc(zl & (uint32_t)k) & 1) pj.x = -pj.x, pj.y = -pj.y;
+        if (__popc(zl & (uint32_t)j) & 1) pk.x = -pk.x, pk.y = -pk.y;
+        x[j].x = ar * xj.x - ai * xj.y + pj.x;
+        x[j].y = ar * xj.y + ai * xj.x + pj.y;
+        x[k].x = ar * xk.x - ai * xk.y + pk.x;
+        x[k].y = ar * xk.y + ai * xk.x + pk.y;
+    }
+}
+
 // Real matrix: only the real parts of the entries are read (two multiplies per entry).
 template <int B, typename V, typename M>
 __device__ __forceinline__ void reg_real1(V *x, const M &m) {
@@ -197,18 +222,31 @@ __device__ __forceinline__ void reg_real2(V *x, CPtr<R> m) {
 __device__ __forceinline__ int gi_k(uint32_t i) { return 1 + (int)(i & 1u); }
 __device__ __forceinline__ int gi_t0(uint32_t i) { return (int)((i >> 1) & 3u); }
 __device__ __forceinline__ int gi_t1(uint32_t i) { return (int)((i >> 3) & 3u); }
-__device__ __forceinline__ int gi_form(uint32_t i) { return (int)((i >> 5) & 3u); }
-__device__ __forceinline__ uint32_t gi_xl(uint32_t i) { return (i >> 7) & 7u; }
-__device__ __forceinline__ uint32_t gi_zl(uint32_t i) { return (i >> 10) & 7u; }
-__device__ __forceinline__ bool gi_param(uint32_t i) { return (i >> 13) & 1u; }
+__device__ __forceinline__ int gi_form(uint32_t i) { return (int)((i >> 5) & 7u); }
+__device__ __forceinline__ uint32_t gi_xl(uint32_t i) { return (i >> 8) & 7u; }
+__device__ __forceinline__ uint32_t gi_zl(uint32_t i) { return (i >> 11) & 7u; }
+__device__ __forceinline__ bool gi_param(uint32_t i) { return (i >> 14) & 1u; }
 
 // One gate of a sweep: `c` holds the first eight reals of its matrix entry
 // (read ahead), `m` points at the whole entry (two-qubit dense forms).
 template <typename V, typename R>
 __device__ __forceinline__ void reg_apply(uint32_t info, V *x, const Coef8<R> &c, CPtr<R> m) {
     const int k = gi_k(info), t0 = gi_t0(info), t1 = gi_t1(info), form = gi_form(info);
+    if (form == BF_PAULI) {
+        const uint32_t zl = gi_zl(info);
+        switch (gi_xl(info)) {
+            case 1: reg_pauli<1>(x, c, zl); break;
+            case 2: reg_pauli<2>(x, c, zl); break;
+            case 3: reg_pauli<3>(x, c, zl); break;
+            case 4: reg_pauli<4>(x, c, zl); break;
+            case 5: reg_pauli<5>(x, c, zl); break;
+            case 6: reg_pauli<6>(x, c, zl); break;
+            default: reg_pauli<7>(x, c, zl); break;
+        }
+        return;
+    }
     if (form == BF_SIGN) {
-        const uint32_t neg = (info >> 14) & 15u;
+        const uint32_t neg = (info >> 15) & 15u;
         if (k == 1) {
             switch (t0) {
                 case 0: reg_sign<0, -1>(x, neg); break;
