@@ -479,7 +479,10 @@ cast_status batch_traffic(const cast_batch *b, double *alg_bytes, uint64_t *stat
 
 /* The segments batch_create cuts one instance's gate list into (host only,
  * no device work): gates whose qubits together fit one LDS tile of 2^tb
- * amplitudes (tb = min(n, batch_tile_bits), the tuning knob, 11 by default), at
+ * amplitudes (tb = min(n, batch_tile_bits), the tuning knob, 11 by default)
+ * with at most tb - w of them at or above bit w (w = batch_min_window, 2 for
+ * CAST_C128 and 3 for CAST_C64 by default, at most tb - 2), so that every
+ * tile is read in runs of at least 2^w consecutive amplitudes, at
  * most 64 gates each, forward (reverse = 0) or for the reverse adjoint sweep
  * (reverse = 1).  Segments may take gates out of circuit order: two gates
  * that share a qubit keep their relative order unless both are diagonal;

@@ -249,7 +249,7 @@ TUNING_KEYS = ("direct_min_q", "tile_bits", "direct_ipt", "direct_nt", "direct_c
                "diag_order", "blocked_tile_bits", "blocked_threads", "mfma_3m_min_d", "mfma_low_tile",
                "persistent_spin_limit", "diag_run_tables", "diag_run_qubits", "diag_run_unroll", "diag_run_grid",
                "diag_run_lds", "mfma_prefetch", "diag_spread", "diag_run_reuse", "direct_rot", "direct_rot_lo",
-               "direct_rot_hi", "batch_tile_bits")
+               "direct_rot_hi", "batch_tile_bits", "batch_min_window")
 PATH_COST_KEYS = tuple(f"bw{i}" for i in range(7)) + ("fl4", "fl5", "fl6", "fl_vec", "launch_ms", "seg_bw") + \
     tuple(f"seg_gate{d}" for d in range(4))
 #: environment overrides (set for sweeps) take precedence over the tuning file

@@ -264,6 +264,7 @@ def main():
         # the batched programs' tile size is measured on the batch workloads
         # (bench.py --vqa-only / --tfim-only), not on this suite: carried over
         result["knobs"][dname]["batch_tile_bits"] = cast.get_tuning("batch_tile_bits", dtype)
+        result["knobs"][dname]["batch_min_window"] = cast.get_tuning("batch_min_window", dtype)
         log(f"{dname}: cost table (ms per 2^30 amplitudes)")
         result["cost"][dname] = cost_table(args.n, dtype, log)
         log(f"{dname}: path costs")

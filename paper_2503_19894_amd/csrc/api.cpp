@@ -531,6 +531,7 @@ static int *tuning_field(const std::string &key, cast_dtype dt, int *lo, int *hi
     if (key == "direct_rot_lo") { *hi = 34; return &t.direct_rot_lo[i]; }
     if (key == "direct_rot_hi") { *hi = 34; return &t.direct_rot_hi[i]; }
     if (key == "batch_tile_bits") { *lo = 4; *hi = 12; return &t.batch_tile_bits[i]; }
+    if (key == "batch_min_window") { *hi = 10; return &t.batch_min_window[i]; }
     return nullptr;
 }
 

@@ -240,6 +240,15 @@ static int batch_tile_bits(cast_dtype dt) {
     return tb;
 }
 
+// Low window a segment's tile keeps (the knob batch_min_window, at most
+// tb - 2 so that a two-qubit gate on high qubits still fits);
+// CAST_BATCH_MIN_WINDOW overrides.
+static int batch_min_window(cast_dtype dt, int tb) {
+    int w = tuning().batch_min_window[dt == CAST_C64 ? CAST_C64 : CAST_C128];
+    if (const char *e = std::getenv("CAST_BATCH_MIN_WINDOW")) w = atoi(e);
+    return std::max(0, std::min(w, tb - 2));
+}
+
 // Whether segments may take gates out of circuit order (CAST_BATCH_REORDER=0
 // keeps the circuit order).
 static bool batch_reorder() {
@@ -310,8 +319,16 @@ static std::vector<int> cluster_sweeps(const std::vector<int> &seg, const std::v
 }
 
 static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &gmask, const std::vector<char> &gdiag,
-                                                   int tb, bool reverse, bool reorder) {
+                                                   int tb, bool reverse, bool reorder, int wmin) {
     const int L = (int)gmask.size();
+    // a segment's qubits fit a tile of 2^tb amplitudes whose low window
+    // [0, W) keeps at least wmin bits: at most tb - wmin of them lie at or
+    // above bit wmin, so the tile is read in runs of at least 2^wmin
+    // consecutive amplitudes
+    const uint64_t hi_mask = wmin >= 64 ? 0 : ~((1ull << wmin) - 1);
+    auto fits = [&](uint64_t q) {
+        return __builtin_popcountll(q) <= tb && __builtin_popcountll(q & hi_mask) <= tb - wmin;
+    };
     auto gate_at = [&](int p) { return reverse ? L - 1 - p : p; };   // base order position -> gate
     std::vector<std::vector<int>> segs;
     if (!reorder) {
@@ -319,7 +336,7 @@ static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &
         uint64_t qm = 0;
         for (int p = 0; p < L; ++p) {
             const int l = gate_at(p);
-            if (!cur.empty() && (__builtin_popcountll(qm | gmask[l]) > tb || cur.size() >= (size_t)kSegMaxGates)) {
+            if (!cur.empty() && (!fits(qm | gmask[l]) || cur.size() >= (size_t)kSegMaxGates)) {
                 segs.push_back(cur);
                 cur.clear();
                 qm = 0;
@@ -372,7 +389,7 @@ static std::vector<std::vector<int>> segment_gates(const std::vector<uint64_t> &
             for (size_t r = 0; r < ready.size() && pick < 0; ++r)
                 if (!(gmask[gate_at(ready[r])] & ~qm)) pick = (int)r;
             for (size_t r = 0; r < ready.size() && pick < 0; ++r)
-                if (__builtin_popcountll(qm | gmask[gate_at(ready[r])]) <= tb) pick = (int)r;
+                if (fits(qm | gmask[gate_at(ready[r])])) pick = (int)r;
             if (pick < 0) break;
             const int p = ready[pick];
             ready.erase(ready.begin() + pick);
@@ -535,7 +552,9 @@ cast_status batch_create(int n_inst, const int *n_qubits, cast_dtype dt, const c
             for (int a = 0; a < ip.gates[l].k; ++a) gmask[l] |= 1ull << ip.gates[l].qubits[a];
             gdiag[l] = ip.form[l] == BF_DIAG || ip.form[l] == BF_SIGN;
         }
-        auto segment = [&](bool reverse) { return segment_gates(gmask, gdiag, ip.tb, reverse, batch_reorder()); };
+        auto segment = [&](bool reverse) {
+            return segment_gates(gmask, gdiag, ip.tb, reverse, batch_reorder(), batch_min_window(dt, ip.tb));
+        };
         for (auto &sg : segment(false)) {
             ip.ops.push_back(HostOp{BK_FWD, -1, -1});
             ip.seg_gates.push_back(sg);
@@ -935,7 +954,8 @@ cast_status batch_segments(int n, const cast_gate *gates, size_t n_gates, cast_d
         gdiag[l] = diag;
     }
     const std::vector<std::vector<int>> segs =
-        segment_gates(gmask, gdiag, std::min(n, batch_tile_bits(dt)), reverse != 0, batch_reorder());
+        segment_gates(gmask, gdiag, std::min(n, batch_tile_bits(dt)), reverse != 0, batch_reorder(),
+                      batch_min_window(dt, std::min(n, batch_tile_bits(dt))));
     *n_segments = segs.size();
     size_t i = 0;
     for (size_t sgi = 0; sgi < segs.size(); ++sgi)

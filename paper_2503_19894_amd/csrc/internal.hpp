@@ -106,6 +106,9 @@ struct Tuning {                      // launch parameters, by dtype index (CAST_
     int direct_rot_hi[3] = {0, 25, 25};
     // batched programs: log2 amplitudes of a segment's LDS tile
     int batch_tile_bits[3] = {0, 11, 11};
+    // batched programs: low bits every segment's tile keeps (runs of 2^w
+    // consecutive amplitudes per tile load)
+    int batch_min_window[3] = {0, 2, 3};
 };
 Tuning &tuning();
 // Predicted ms per 2^30 amplitudes of a (k, d) pass, by dtype (cost_table_set).
