@@ -1,5 +1,6 @@
 """Segments of the batched programs (host planning, no GPU): every segment
-fits one LDS tile and at most 64 gates, the segments cover every gate once,
+fits one LDS tile that keeps its low window (batch_min_window) and at most
+64 gates, the segments cover every gate once,
 gates that share a qubit keep their circuit order unless both are diagonal,
 and the reordered circuit is the same operator (checked by the oracle on
 small instances).  On the layered ansatz and the Trotter circuit the
@@ -33,9 +34,13 @@ def _check(n, gates, dtype, reverse):
     flat = [l for s in segs for l in s]
     assert sorted(flat) == list(range(len(gates)))
     tb = min(n, TB[dtype])
+    w = max(0, min(cast.get_tuning("batch_min_window", dtype), tb - 2))
     for s in segs:
         assert 1 <= len(s) <= 64
-        assert len(set().union(*(_qubits(gates[l]) for l in s))) <= tb
+        qs = set().union(*(_qubits(gates[l]) for l in s))
+        assert len(qs) <= tb
+        # the tile keeps a low window of w bits: at most tb - w qubits at or above bit w
+        assert len([q for q in qs if q >= w]) <= tb - w
     pos = {l: i for i, l in enumerate(flat)}
     for a in range(len(gates)):
         for b in range(a + 1, len(gates)):
