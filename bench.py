@@ -461,10 +461,12 @@ def run_blocked(sv, psi, fc, n, dtype, state_bytes, steps, warmup, per_pass_ms):
     }
 
 
-def run_dense(n=32, depth=20, steps=1, warmup=1):
+def run_dense(n=32, depth=20, steps=1, warmup=1, tune_reps=2):
     """Dense random circuit (20 layers of Haar gates on 6- and 5-qubit random
     subsets, complex128, from |0...0>): per-pass kernel throughput; dense
-    6-qubit passes are FP64-compute-bound, 5-qubit passes HBM-bound."""
+    6-qubit passes are FP64-compute-bound, 5-qubit passes HBM-bound.  With
+    tune_reps > 0 the 5-qubit passes' unit order is first chosen per pass by
+    measurement (circuit_tune), then the state is reset."""
     import numpy as np
     import torch
 
@@ -477,14 +479,26 @@ def run_dense(n=32, depth=20, steps=1, warmup=1):
     psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
     psi[0] = 1
     sv = cast.StateVector(n, tensor=psi)
+    tune = None
+    if tune_reps > 0:
+        t0 = time.perf_counter()
+        before, after = sv.tune_circuit(fc, reps=tune_reps)
+        rots = [fc.pass_shape(torch.complex128, i)[0] for i, inf in enumerate(infos) if inf["kernel"] == 4]
+        tune = {"reps": tune_reps, "s": round(time.perf_counter() - t0, 3), "ms_before": round(before, 3),
+                "ms_after": round(after, 3), "rot_counts": {str(r): rots.count(r) for r in sorted(set(rots))}}
+        psi.zero_()
+        psi[0] = 1
     for _ in range(warmup):
         sv.apply_circuit(fc)
     torch.cuda.synchronize()
     per = np.zeros(len(infos))
+    region_marker()
     t0 = time.perf_counter()
     for _ in range(steps):
         per += sv.apply_circuit_timed(fc)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    region_marker()
     per /= steps
     kern = {}
     for inf, ms in zip(infos, per):
@@ -502,7 +516,7 @@ def run_dense(n=32, depth=20, steps=1, warmup=1):
     nrm = float(torch.linalg.vector_norm(psi))
     del sv, psi
     torch.cuda.empty_cache()
-    return {"n_qubits": n, "passes": len(fc), "s_per_circuit": wall / steps,
+    return {"n_qubits": n, "passes": len(fc), "s_per_circuit": wall / steps, "tune": tune,
             "event_s_per_circuit": float(per.sum()) / 1e3, "norm_after": nrm, "kernels": kern,
             "fp64_roof_s": sum(i["flops"] for i in infos) / 78.6e12,
             "hbm_roof_s": sum(i["alg_bytes"] for i in infos) / 8e12}

@@ -197,10 +197,13 @@ cast_status circuit_passes(const cast_fused *f, int n, cast_dtype dt, size_t *n_
 cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
                               int *kernel, int *tables, double *alg_bytes, double *flops);
 
-/* Launch shapes of the direct passes (kernel 0).  A direct pass walks its
- * (group, block) work items in runs of 2^chunk_log groups of one block and
- * visits its 2^it_bits iterations in an order rotated left by rot bits
- * (rot 0: address order; needs a power-of-two iteration count, else 0).
+/* Launch shapes of the direct passes (kernel 0) and of the matrix-core
+ * direct passes of 16- and 32-dimensional blocks when mfma_prefetch is 2.  A
+ * direct pass walks its (group, block) work items in runs of 2^chunk_log
+ * groups of one block and visits its 2^it_bits iterations in an order rotated
+ * left by rot bits (rot 0: address order; needs a power-of-two iteration
+ * count, else 0).  A matrix-core pass takes only rot: it rotates the order of
+ * its runs of four 16-group units (chunk_log is ignored).
  * Which rate a shape reaches depends on how the gate's planes fall onto the
  * DRAM channels and banks, so no one knob value suits every pass (the
  * paper's cost model is likewise measured, Sec. III-C).  The shape is kept
@@ -218,19 +221,21 @@ cast_status circuit_set_pass_shape(cast_fused *f, int n, cast_dtype dt, size_t i
 
 /* Chooses each direct pass's launch shape by measurement on sv's device:
  * the knobs' shape, run lengths 2^8, 2^10 and 2^12 groups, then rotations
- * 2, 4 and 6 at the best run length, each launched reps times (1..100; the
- * minimum counts); a shape other than the knobs' is kept only when it is more
- * than 1 % faster.  The passes are applied to sv in place, so its amplitudes
- * change (they stay normalised: every pass is unitary).  *before_ms and
- * *after_ms (may be NULL) receive the summed minimum times of the direct
- * passes with the knobs' shapes and with the chosen ones.  Synchronous.  The
- * shapes live in the list: do not tune a list while another thread applies
- * it (the same holds for circuit_set_pass_shape). */
+ * 2, 4 and 6 at the best run length (matrix-core passes that take a shape:
+ * the knobs' shape and rotations 2, 4, 6 and 8), each launched reps times
+ * (1..100; the minimum counts); a shape other than the knobs' is kept only
+ * when it is more than 1 % faster.  The passes are applied to sv in place,
+ * so its amplitudes change (they stay normalised: every pass is unitary).
+ * *before_ms and *after_ms (may be NULL) receive the summed minimum times of
+ * the tuned passes with the knobs' shapes and with the chosen ones.
+ * Synchronous.  The shapes live in the list: do not tune a list while
+ * another thread applies it (the same holds for circuit_set_pass_shape). */
 cast_status circuit_tune(cast_sv *sv, cast_fused *f, int reps, double *before_ms, double *after_ms);
 
 /* How fused gate i runs on a 2^n state of dtype dt: *kernel = 0 (direct
- * gather), 1 (LDS tile), 2 (LDS tile, two buffers), 3 (elementwise diagonal)
- * or -1 (identity, skipped), *d the block dimension,
+ * gather), 1 (LDS tile), 2 (LDS tile, two buffers), 3 (elementwise diagonal),
+ * 4 (matrix-core direct gather), 5 (matrix-core LDS tile) or -1 (identity,
+ * skipped), *d the block dimension,
  * and the pass's algorithmic HBM bytes (every amplitude of a non-identity
  * block read once and written once) and flops (8 per complex multiply-add
  * over the non-identity blocks). */

@@ -807,23 +807,30 @@ cast_status circuit_tune(cast_sv *sv, cast_fused *fc, int reps, double *before_m
     double before = 0, after = 0;
     for (size_t i = 0; i < sc->passes.size() && !rc; ++i) {
         SchedPass &sp = sc->passes[i];
-        if (sp.kind != 0 || pass_kernel_kind(n, dt, f->plans[sp.first]) != 0) continue;
-        const int k = f->plans[sp.first].k;
-        // the knobs' shape first, then run lengths, then rotations at the best run length
+        if (sp.kind != 0 && sp.kind != 4) continue;
+        const PassPlan &pl = f->plans[sp.first];
+        const int kind = pass_kernel_kind(n, dt, pl);
+        // matrix-core direct passes take a rotation only in the next-unit prefetch kernel
+        const bool mfma = kind == 4 && tu.mfma_prefetch[dt] >= 2 && pl.d < 6;
+        if (kind != 0 && !mfma) continue;
+        const int k = pl.k;
+        // the knobs' shape first, then run lengths (direct passes), then
+        // rotations at the best run length (8 for matrix-core passes only)
         const PassShape knob{-1, -1};
         double t_knob = 0;
         if ((rc = time_shape(sp, knob, &t_knob))) break;
         PassShape best = knob;
         double t_best = t_knob;
-        int best_cl = std::min(std::max(tu.direct_chunk_log[dt], 6), n - k);
+        int best_cl = mfma ? -1 : std::min(std::max(tu.direct_chunk_log[dt], 6), n - k);
         for (int cl : {8, 10, 12}) {
-            if (cl > n - k || cl == best_cl) continue;
+            if (mfma || cl > n - k || cl == best_cl) continue;
             double t = 0;
             if ((rc = time_shape(sp, PassShape{0, cl}, &t))) break;
             if (t < t_best) t_best = t, best = PassShape{0, cl}, best_cl = cl;
         }
-        for (int rot : {2, 4, 6}) {
+        for (int rot : {2, 4, 6, 8}) {
             if (rc) break;
+            if (rot == 8 && !mfma) continue;
             double t = 0;
             if ((rc = time_shape(sp, PassShape{rot, best_cl}, &t))) break;
             if (t < t_best) t_best = t, best = PassShape{rot, best_cl};

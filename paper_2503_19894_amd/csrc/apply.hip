@@ -668,7 +668,11 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
 // k_mfma_direct with the inputs of a wave's next unit requested before the
 // matrix-core products of the current one, so a wave's memory traffic
 // overlaps its own products instead of alternating with them (the products
-// of a 32-dimensional block take about as long as its loads).
+// of a 32-dimensional block take about as long as its loads).  The state is
+// streamed with non-temporal loads and stores.  a.rot > 0 rotates the index
+// of each run of four units (one workgroup's) left by a.rot bits within
+// 2^a.it_bits runs, so the workgroups in flight spread over more DRAM rows of
+// every plane; the host sets it only when the run count is 2^it_bits.
 template <int D, typename R, bool M3>
 __global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, const R *__restrict__ mat,
                                                         PassArgs a) {
@@ -684,7 +688,12 @@ __global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, c
     const uint64_t stride = (uint64_t)gridDim.x * 4;
     // group base and block slot of unit u
     auto locate = [&](uint64_t u, uint32_t &bs) {
-        const uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        if (a.rot) {
+            uint32_t w = uu >> 2;
+            w = ((w << a.rot) | (w >> (a.it_bits - a.rot))) & ((1u << a.it_bits) - 1);
+            uu = (w << 2) | (uu & 3u);
+        }
         const uint32_t gu = uu / a.nblk;
         bs = uu - gu * a.nblk;
         const uint64_t g = (uint64_t)gu * 16 + j;
@@ -700,7 +709,7 @@ __global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, c
     uint64_t base = locate(u, bs);
     V xs[N / 4];
 #pragma unroll
-    for (int s = 0; s < N / 4; ++s) xs[s] = psi[base ^ off_of<D>(a.off, 4 * s + kk)];
+    for (int s = 0; s < N / 4; ++s) xs[s] = ld<true>(psi + (base ^ off_of<D>(a.off, 4 * s + kk)));
     for (;;) {
         const uint64_t un = u + stride;
         const bool more = un < units;
@@ -710,10 +719,10 @@ __global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, c
         if (more) {
             basen = locate(un, bsn);
 #pragma unroll
-            for (int s = 0; s < N / 4; ++s) xn[s] = psi[basen ^ off_of<D>(a.off, 4 * s + kk)];
+            for (int s = 0; s < N / 4; ++s) xn[s] = ld<true>(psi + (basen ^ off_of<D>(a.off, 4 * s + kk)));
         }
-        auto st = [&](int row, const V &y) { psi[base ^ off_of<D>(a.off, row)] = y; };
-        mfma_core<D, R, M3>(mt + (size_t)bs * N * N, xs, st);
+        auto sto = [&](int row, const V &y) { st<true>(psi + (base ^ off_of<D>(a.off, row)), y); };
+        mfma_core<D, R, M3>(mt + (size_t)bs * N * N, xs, sto);
         if (!more) break;
         u = un;
         bs = bsn;
@@ -1036,6 +1045,17 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             grid = (units + 3) / 4;
             const uint64_t cap = (uint64_t)tu.mfma_grid_per_cu[dt] * 256;
             if (grid > cap) grid = cap;
+            // rotated order of the four-unit runs (next-unit prefetch kernel only)
+            const int rot = shape && shape->rot > 0 ? shape->rot : 0;
+            if (rot > 0 && tu.mfma_prefetch[dt] >= 2 && D < 6 && units % 4 == 0) {
+                const uint64_t runs = units / 4;
+                int bits = 0;
+                while ((1ull << bits) < runs) ++bits;
+                if ((1ull << bits) == runs && rot < bits) {
+                    a.rot = rot;
+                    a.it_bits = bits;
+                }
+            }
         } else {
             const int tb = mfma_tile_bits(n, dt, p);
             const int khi = mfma_tile_khi(n, dt, p);

@@ -175,7 +175,7 @@ struct SchedPass {
     std::vector<PhaseTable> tabs;    // kind 6
     size_t tab_off = 0;              // kind 6: entry offset of its tables in the device buffer
     double active_amps = 0;          // kind 6: amplitudes at which some table differs from 1
-    PassShape shape;                 // kind 0: launch shape (circuit_tune)
+    PassShape shape;                 // kinds 0 and 4: launch shape (circuit_tune)
 };
 struct Schedule {
     int n = 0;

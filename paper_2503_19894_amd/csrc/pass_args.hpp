@@ -20,7 +20,7 @@ struct PassArgs {
     int W;                  // tile: contiguous window bits
     int khi, klo;           // tile: targets at/above and below W
     int qhi[6];             // tile: high targets, ascending
-    int rot, it_bits;       // direct: iteration order rotated left by rot bits of it_bits (rot 0: in order)
+    int rot, it_bits;       // direct (iterations) and matrix-core direct (four-unit runs): order rotated left by rot bits of it_bits (rot 0: in order)
 };
 
 // Kernel argument block of a diagonal pass (every block 1 x 1).
