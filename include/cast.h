@@ -198,13 +198,12 @@ cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t 
                               int *kernel, int *tables, double *alg_bytes, double *flops);
 
 /* Launch shapes of the direct passes (kernel 0) and of the matrix-core
- * direct passes of 16- and 32-dimensional blocks when mfma_prefetch is 2.  A
- * direct pass walks its (group, block) work items in runs of 2^chunk_log
- * groups of one block and visits its 2^it_bits iterations in an order rotated
- * left by rot bits (rot 0: address order; needs a power-of-two iteration
- * count, else 0).  A matrix-core pass takes only rot: it rotates the order of
- * its runs of four 16-group units (chunk_log is ignored).
- * Which rate a shape reaches depends on how the gate's planes fall onto the
+ * direct passes (kernel 4).  A direct pass walks its (group, block) work
+ * items in runs of 2^chunk_log groups of one block and visits its 2^it_bits
+ * iterations in an order rotated left by rot bits (rot 0: address order;
+ * needs a power-of-two iteration count, else 0).  A matrix-core pass takes
+ * only rot: it rotates the order of its runs of four 16-group units (chunk_log
+ * is ignored).  Which rate a shape reaches depends on how the gate's planes fall onto the
  * DRAM channels and banks, so no one knob value suits every pass (the
  * paper's cost model is likewise measured, Sec. III-C).  The shape is kept
  * per pass in the list's schedule for (n, dt); -1 means the knob's value
@@ -221,8 +220,8 @@ cast_status circuit_set_pass_shape(cast_fused *f, int n, cast_dtype dt, size_t i
 
 /* Chooses each direct pass's launch shape by measurement on sv's device:
  * the knobs' shape, run lengths 2^8, 2^10 and 2^12 groups, then rotations
- * 2, 4 and 6 at the best run length (matrix-core passes that take a shape:
- * the knobs' shape and rotations 2, 4, 6 and 8), each launched reps times
+ * 2, 4 and 6 at the best run length (matrix-core direct passes: the knobs'
+ * shape and rotations 2, 4, 6 and 8), each launched reps times
  * (1..100; the minimum counts); a shape other than the knobs' is kept only
  * when it is more than 1 % faster.  The passes are applied to sv in place,
  * so its amplitudes change (they stay normalised: every pass is unitary).

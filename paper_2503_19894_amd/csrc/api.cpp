@@ -810,8 +810,7 @@ cast_status circuit_tune(cast_sv *sv, cast_fused *fc, int reps, double *before_m
         if (sp.kind != 0 && sp.kind != 4) continue;
         const PassPlan &pl = f->plans[sp.first];
         const int kind = pass_kernel_kind(n, dt, pl);
-        // matrix-core direct passes take a rotation only in the next-unit prefetch kernel
-        const bool mfma = kind == 4 && tu.mfma_prefetch[dt] >= 2 && pl.d < 6;
+        const bool mfma = kind == 4;   // matrix-core direct: unit-order rotation only
         if (kind != 0 && !mfma) continue;
         const int k = pl.k;
         // the knobs' shape first, then run lengths (direct passes), then

@@ -651,7 +651,12 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
     // the block slot varies fastest across units (as in the direct kernel);
     // units number below 2^26 for n <= 34
     for (uint64_t u = (uint64_t)blockIdx.x * 4 + wave; u < units; u += (uint64_t)gridDim.x * 4) {
-        const uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        uint32_t uu = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        if (a.rot) {   // rotated order of the four-unit runs, as in k_mfma_direct_db
+            uint32_t w = uu >> 2;
+            w = ((w << a.rot) | (w >> (a.it_bits - a.rot))) & ((1u << a.it_bits) - 1);
+            uu = (w << 2) | (uu & 3u);
+        }
         const uint32_t gu = uu / a.nblk;
         const uint32_t bs = uu - gu * a.nblk;
         const uint64_t g = (uint64_t)gu * 16 + j;
@@ -669,10 +674,11 @@ __global__ void __launch_bounds__(256) k_mfma_direct(R *__restrict__ psi_r, cons
 // matrix-core products of the current one, so a wave's memory traffic
 // overlaps its own products instead of alternating with them (the products
 // of a 32-dimensional block take about as long as its loads).  The state is
-// streamed with non-temporal loads and stores.  a.rot > 0 rotates the index
-// of each run of four units (one workgroup's) left by a.rot bits within
-// 2^a.it_bits runs, so the workgroups in flight spread over more DRAM rows of
-// every plane; the host sets it only when the run count is 2^it_bits.
+// streamed with non-temporal loads and stores.  In both matrix-core direct
+// kernels a.rot > 0 rotates the index of each run of four units (one
+// workgroup's) left by a.rot bits within 2^a.it_bits runs, so the workgroups
+// in flight spread over more DRAM rows of every plane; the host sets it only
+// when the run count is 2^it_bits.
 template <int D, typename R, bool M3>
 __global__ void __launch_bounds__(256) k_mfma_direct_db(R *__restrict__ psi_r, const R *__restrict__ mat,
                                                         PassArgs a) {
@@ -1045,9 +1051,9 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             grid = (units + 3) / 4;
             const uint64_t cap = (uint64_t)tu.mfma_grid_per_cu[dt] * 256;
             if (grid > cap) grid = cap;
-            // rotated order of the four-unit runs (next-unit prefetch kernel only)
+            // rotated order of the four-unit runs
             const int rot = shape && shape->rot > 0 ? shape->rot : 0;
-            if (rot > 0 && tu.mfma_prefetch[dt] >= 2 && D < 6 && units % 4 == 0) {
+            if (rot > 0 && units % 4 == 0) {
                 const uint64_t runs = units / 4;
                 int bits = 0;
                 while ((1ull << bits) < runs) ++bits;

@@ -249,50 +249,51 @@ def test_pass_shapes_and_tuner(dtype):
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
 def test_mfma_pass_rotation(dtype):
-    """Rotated unit order of the matrix-core direct passes (next-unit
-    prefetch form, also forced for complex64): shapes set by hand, including
-    rotations the host must ignore (at or above the run count's bits), and the
-    shapes the tuner picks give bitwise the same state as the knobs' order and
-    match the oracle."""
+    """Rotated unit order of the matrix-core direct passes, in every input
+    load mode: shapes set by hand, including rotations the host must ignore
+    (at or above the run count's bits), and the shapes the tuner picks give
+    bitwise the same state as the knobs' order and match the oracle."""
     n = 17
     rng = np.random.default_rng(37)
     gates = [Gate("unitary", (0, 3, 8, 12, 16), matrix=haar_unitary(32, rng)),
              Gate("unitary", (1, 4, 7, 10, 14, 11),
                   matrix=np.kron(np.diag(np.exp(1j * rng.uniform(0.1, 6.0, 2))), haar_unitary(32, rng))),
              Gate("unitary", (2, 5, 9, 13, 15), matrix=haar_unitary(32, rng)),
-             Gate("unitary", (6, 12, 15, 16), matrix=haar_unitary(16, rng))]
+             Gate("unitary", (6, 12, 15, 16), matrix=haar_unitary(16, rng)),
+             Gate("unitary", (0, 5, 8, 10, 13, 16), matrix=haar_unitary(64, rng))]
     psi0 = random_state(n, seed=9, workload=3)
     want = oracle.run_circuit(n, gates, psi0)
     keep = cast.get_tuning("mfma_prefetch", dtype)
-    cast.set_tuning("mfma_prefetch", 2, dtype)
     try:
-        fc = cast.FusedCircuit(n, gates, k_max=6)
-        sched = fc.schedule(dtype)
-        mf = [i for i, p in enumerate(sched) if p["kernel"] == 4]
-        assert len(mf) >= 2, sched
-        sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
-        sv.apply_circuit(fc)
-        ref = sv.tensor.clone()
-        for rots in ((1, 3, 5, 2), (6, 9, 16, 4)):
-            for j, i in enumerate(mf):
-                fc.set_pass_shape(dtype, i, rots[j % len(rots)], -1)
+        for pre in (0, 1, 2):
+            cast.set_tuning("mfma_prefetch", pre, dtype)
+            fc = cast.FusedCircuit(n, gates, k_max=6)
+            sched = fc.schedule(dtype)
+            mf = [i for i, p in enumerate(sched) if p["kernel"] == 4]
+            assert len(mf) >= 2, sched
+            sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
+            sv.apply_circuit(fc)
+            ref = sv.tensor.clone()
+            for rots in ((1, 3, 5, 2), (6, 9, 16, 4)):
+                for j, i in enumerate(mf):
+                    fc.set_pass_shape(dtype, i, rots[j % len(rots)], -1)
+                sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
+                sv.apply_circuit(fc)
+                torch.cuda.synchronize()
+                assert torch.equal(sv.tensor, ref), rots
+            for i in mf:
+                fc.set_pass_shape(dtype, i, -1, -1)
+            before, after = sv.tune_circuit(fc, reps=2)
+            chosen = [fc.pass_shape(dtype, i) for i in mf]
+            assert all(c[0] in (-1, 2, 4, 6, 8) for c in chosen), chosen
             sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
             sv.apply_circuit(fc)
             torch.cuda.synchronize()
-            assert torch.equal(sv.tensor, ref), rots
-        for i in mf:
-            fc.set_pass_shape(dtype, i, -1, -1)
-        before, after = sv.tune_circuit(fc, reps=2)
-        chosen = [fc.pass_shape(dtype, i) for i in mf]
-        assert all(c[0] in (-1, 2, 4, 6, 8) for c in chosen), chosen
-        sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
-        sv.apply_circuit(fc)
-        torch.cuda.synchronize()
-        note(f"matrix-core rotation {dtype}: passes {mf}, tuned {chosen}, ms {before:.4f} -> {after:.4f}")
-        assert 0 < after <= before
-        assert torch.equal(sv.tensor, ref)
-        err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
-        assert err <= TOL[dtype]
+            note(f"matrix-core rotation {dtype} prefetch {pre}: passes {mf}, tuned {chosen}, ms {before:.4f} -> {after:.4f}")
+            assert 0 < after <= before
+            assert torch.equal(sv.tensor, ref)
+            err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
+            assert err <= TOL[dtype]
     finally:
         cast.set_tuning("mfma_prefetch", keep, dtype)
 
