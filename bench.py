@@ -118,13 +118,13 @@ def run_gpu(n, k_max, dtype_name, steps, warmup, seed=0, tune_reps=3):
     sv = cast.StateVector(n, tensor=psi)
     tune = None
     if tune_reps > 0:
-        # launch shapes of the direct passes, measured on this state (which
-        # the tuner changes), then the input again
+        # launch shapes of the direct, matrix-core and diagonal-run passes,
+        # measured on this state (which the tuner changes), then the input again
         t0 = time.perf_counter()
         before, after = sv.tune_circuit(fc, reps=tune_reps)
-        tune = {"reps": tune_reps, "s": round(time.perf_counter() - t0, 3), "direct_ms_before": round(before, 4),
-                "direct_ms_after": round(after, 4),
-                "shapes": {i: list(fc.pass_shape(dtype, i)) for i, inf in enumerate(infos) if inf["kernel"] == 0}}
+        tune = {"reps": tune_reps, "s": round(time.perf_counter() - t0, 3), "tuned_ms_before": round(before, 4),
+                "tuned_ms_after": round(after, 4),
+                "shapes": {i: list(fc.pass_shape(dtype, i)) for i, inf in enumerate(infos) if inf["kernel"] in (0, 4, 6)}}
         psi.copy_(random_state_torch(n, seed=seed, device="cuda", dtype=dtype))
     for _ in range(warmup):
         sv.apply_circuit(fc)

@@ -475,9 +475,9 @@ class StateVector:
         return np.array(out[:nf], dtype=np.float64)
 
     def tune_circuit(self, fused: FusedCircuit, reps=3):
-        """Measures and keeps each direct pass's launch shape (circuit_tune);
-        changes this state's amplitudes.  Returns (ms before, ms after) of
-        the direct passes."""
+        """Measures and keeps the launch shape of each direct, matrix-core
+        direct and diagonal-run pass (circuit_tune); changes this state's
+        amplitudes.  Returns (ms before, ms after) of the tuned passes."""
         b, a = ctypes.c_double(), ctypes.c_double()
         circuit_tune(self.handle, fused.handle, int(reps), ctypes.byref(b), ctypes.byref(a))
         return b.value, a.value

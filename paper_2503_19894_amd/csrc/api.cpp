@@ -807,29 +807,32 @@ cast_status circuit_tune(cast_sv *sv, cast_fused *fc, int reps, double *before_m
     double before = 0, after = 0;
     for (size_t i = 0; i < sc->passes.size() && !rc; ++i) {
         SchedPass &sp = sc->passes[i];
-        if (sp.kind != 0 && sp.kind != 4) continue;
+        // diagonal runs in the unit-reuse kernel: unit-order rotation only
+        const bool drun = sp.kind == 6 && tu.diag_run_reuse[dt] > 0 && n > (dt == CAST_C128 ? 8 : 9);
+        if (sp.kind != 0 && sp.kind != 4 && !drun) continue;
         const PassPlan &pl = f->plans[sp.first];
-        const int kind = pass_kernel_kind(n, dt, pl);
-        const bool mfma = kind == 4;   // matrix-core direct: unit-order rotation only
-        if (kind != 0 && !mfma) continue;
+        const int kind = drun ? 6 : pass_kernel_kind(n, dt, pl);
+        // matrix-core direct passes and diagonal runs take a unit-order rotation only
+        const bool rot_only = kind == 4 || drun;
+        if (kind != 0 && !rot_only) continue;
         const int k = pl.k;
         // the knobs' shape first, then run lengths (direct passes), then
-        // rotations at the best run length (8 for matrix-core passes only)
+        // rotations at the best run length (8 for rotation-only passes)
         const PassShape knob{-1, -1};
         double t_knob = 0;
         if ((rc = time_shape(sp, knob, &t_knob))) break;
         PassShape best = knob;
         double t_best = t_knob;
-        int best_cl = mfma ? -1 : std::min(std::max(tu.direct_chunk_log[dt], 6), n - k);
+        int best_cl = rot_only ? -1 : std::min(std::max(tu.direct_chunk_log[dt], 6), n - k);
         for (int cl : {8, 10, 12}) {
-            if (mfma || cl > n - k || cl == best_cl) continue;
+            if (rot_only || cl > n - k || cl == best_cl) continue;
             double t = 0;
             if ((rc = time_shape(sp, PassShape{0, cl}, &t))) break;
             if (t < t_best) t_best = t, best = PassShape{0, cl}, best_cl = cl;
         }
         for (int rot : {2, 4, 6, 8}) {
             if (rc) break;
-            if (rot == 8 && !mfma) continue;
+            if (rot == 8 && !rot_only) continue;
             double t = 0;
             if ((rc = time_shape(sp, PassShape{rot, best_cl}, &t))) break;
             if (t < t_best) t_best = t, best = PassShape{rot, best_cl};

@@ -249,6 +249,7 @@ struct DiagReuseArgs {
     int ntab;
     int tk[kRunMaxTables];
     int tq[kRunMaxTables][kRunMaxQ];
+    int rot, it_bits;       // units visited in an order rotated left by rot of it_bits bits (0: in order)
 };
 
 template <typename R, int G, bool LDS_TAB, int UI>
@@ -282,7 +283,10 @@ __global__ void __launch_bounds__(256) k_diag_run_reuse(R *__restrict__ psi_r, c
         for (int h = 0; h < A; ++h) jl[g][h] = ((uint32_t)g << 8) | jof(g, ((uint64_t)threadIdx.x << S) | (uint64_t)h);
     const uint32_t nin = 1u << a.c;
     const int bshift = a.nf - a.c;
-    for (uint64_t unit = blockIdx.x; unit < a.nunits; unit += gridDim.x) {
+    for (uint64_t unit0 = blockIdx.x; unit0 < a.nunits; unit0 += gridDim.x) {
+        // nunits is 2^it_bits when rot > 0
+        const uint64_t unit =
+            a.rot ? (((unit0 << a.rot) | (unit0 >> (a.it_bits - a.rot))) & (a.nunits - 1)) : unit0;
         const uint64_t o = unit >> bshift, b = unit & ((1ull << bshift) - 1);
         uint64_t xo = 0, xb = 0;   // uniform
         for (int i = 0; i < a.nd; ++i) xo |= ((o >> i) & 1ull) << a.dpos[i];
@@ -703,6 +707,11 @@ cast_status launch_diag_run(void *psi, int n, cast_dtype dt, const SchedPass &p,
         }
         r.c = std::min(r.nf, tu.diag_run_reuse[dt]);
         r.nunits = 1ull << (n - LB - r.c);
+        // the pass's launch shape: units in rotated order
+        if (p.shape.rot > 0 && p.shape.rot < n - LB - r.c) {
+            r.rot = p.shape.rot;
+            r.it_bits = n - LB - r.c;
+        }
         uint64_t grid = std::min<uint64_t>(r.nunits, (uint64_t)tu.diag_run_grid[dt]);
         const size_t off = p.tab_off * 2;
         const bool lds = tu.diag_run_lds[dt] != 0;

@@ -203,8 +203,9 @@ def test_direct_rotated_order(dtype, rot):
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
 def test_pass_shapes_and_tuner(dtype):
-    """Per-pass launch shapes (rotation, block-run length) set by hand on
-    every direct pass, and the shapes the tuner picks: the same circuit
+    """Per-pass launch shapes set by hand on every direct pass (rotation,
+    block-run length) and every diagonal run (rotation, including rotations
+    the host must ignore), and the shapes the tuner picks: the same circuit
     gives bitwise the same state as with the knobs' shapes, and matches the
     oracle."""
     n = 17
@@ -220,7 +221,8 @@ def test_pass_shapes_and_tuner(dtype):
     fc = cast.FusedCircuit(n, gates, k_max=4)
     sched = fc.schedule(dtype)
     direct = [i for i, p in enumerate(sched) if p["kernel"] == 0]
-    assert direct
+    runs = [i for i, p in enumerate(sched) if p["kernel"] == 6]
+    assert direct and runs
     sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     ref = sv.tensor.clone()
@@ -228,19 +230,25 @@ def test_pass_shapes_and_tuner(dtype):
     for j, i in enumerate(direct):
         fc.set_pass_shape(dtype, i, *shapes[j % len(shapes)])
     assert fc.pass_shape(dtype, direct[0]) == shapes[0]
+    run_rots = [1, 3, 6, 7, 12]
+    for j, i in enumerate(runs):
+        fc.set_pass_shape(dtype, i, run_rots[j % len(run_rots)], -1)
     sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     torch.cuda.synchronize()
     assert torch.equal(sv.tensor, ref)
     # the tuner applies passes to the state it is given; then start again
-    for i in direct:
+    for i in direct + runs:
         fc.set_pass_shape(dtype, i, -1, -1)
     before, after = sv.tune_circuit(fc, reps=2)
     chosen = [fc.pass_shape(dtype, i) for i in direct]
+    chosen_runs = [fc.pass_shape(dtype, i)[0] for i in runs]
+    assert all(r in (-1, 2, 4, 6, 8) for r in chosen_runs), chosen_runs
     sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     torch.cuda.synchronize()
-    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, ms {before:.4f} -> {after:.4f}")
+    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, diagonal runs {runs}, tuned {chosen_runs}, "
+         f"ms {before:.4f} -> {after:.4f}")
     assert 0 < after <= before
     assert torch.equal(sv.tensor, ref)
     err = float(np.max(np.abs(sv.numpy().astype(np.complex128) - want)))
