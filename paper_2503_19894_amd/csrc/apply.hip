@@ -355,7 +355,9 @@ __global__ void __launch_bounds__(256) k_tile(R *__restrict__ psi_r, const R *__
     const uint32_t items = (1u << log_gt) * a.nblk;
     const bool batched = chunks >= 8 * 256;           // chunks is a power of two
 
-    for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (uint64_t t0 = blockIdx.x; t0 < a.ntiles; t0 += gridDim.x) {
+        // tiles in an order rotated left by a.rot bits (ntiles = 2^it_bits then)
+        const uint64_t t = a.rot ? (((t0 << a.rot) | (t0 >> (a.it_bits - a.rot))) & (a.ntiles - 1)) : t0;
         // global index of the tile's first amplitude: t above the window,
         // with zeros inserted at the high targets
         const uint64_t tbase = deposit(t << a.W, a.hilowmask, a.khi);
@@ -758,7 +760,9 @@ __global__ void __launch_bounds__(256) k_mfma_tile(R *__restrict__ psi_r, const 
     const uint32_t upb = (1u << log_gt) >> 4;   // units per block in a tile
     const uint32_t units = upb * a.nblk;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, j = lane & 15;
-    for (uint64_t t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    for (uint64_t t0 = blockIdx.x; t0 < a.ntiles; t0 += gridDim.x) {
+        // tiles in an order rotated left by a.rot bits, as in k_tile
+        const uint64_t t = a.rot ? (((t0 << a.rot) | (t0 >> (a.it_bits - a.rot))) & (a.ntiles - 1)) : t0;
         const uint64_t tbase = deposit(t << a.W, a.hilowmask, a.khi);
         for (uint32_t c0 = threadIdx.x; c0 < chunks; c0 += 8 * 256) {
             uint4 buf[8];
@@ -1082,6 +1086,10 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
                 a.toff[i] = o;
             }
             a.ntiles = 1ull << (n - tb);
+            if (shape && shape->rot > 0 && shape->rot < n - tb) {   // rotated tile order
+                a.rot = shape->rot;
+                a.it_bits = n - tb;
+            }
             grid = a.ntiles;
             if (grid > (uint64_t)tu.max_grid[dt]) grid = tu.max_grid[dt];
             lds += ((size_t)1 << tb) * amp_bytes(dt);
@@ -1183,6 +1191,10 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             a.toff[i] = o;
         }
         a.ntiles = 1ull << (n - tb);
+        if (shape && shape->rot > 0 && shape->rot < n - tb) {   // rotated tile order
+            a.rot = shape->rot;
+            a.it_bits = n - tb;
+        }
         const int wg = 256;
         uint64_t grid = a.ntiles;
         if (grid > (uint64_t)tu.max_grid[dt]) grid = tu.max_grid[dt];

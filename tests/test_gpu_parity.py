@@ -204,10 +204,10 @@ def test_direct_rotated_order(dtype, rot):
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
 def test_pass_shapes_and_tuner(dtype):
     """Per-pass launch shapes set by hand on every direct pass (rotation,
-    block-run length) and every diagonal run (rotation, including rotations
-    the host must ignore), and the shapes the tuner picks: the same circuit
-    gives bitwise the same state as with the knobs' shapes, and matches the
-    oracle."""
+    block-run length) and every LDS-tile pass and diagonal run (rotation,
+    including rotations the host must ignore), and the shapes the tuner picks:
+    the same circuit gives bitwise the same state as with the knobs' shapes,
+    and matches the oracle."""
     n = 17
     rng = np.random.default_rng(29)
     gates = qft(n)
@@ -221,8 +221,8 @@ def test_pass_shapes_and_tuner(dtype):
     fc = cast.FusedCircuit(n, gates, k_max=4)
     sched = fc.schedule(dtype)
     direct = [i for i, p in enumerate(sched) if p["kernel"] == 0]
-    runs = [i for i, p in enumerate(sched) if p["kernel"] == 6]
-    assert direct and runs
+    runs = [i for i, p in enumerate(sched) if p["kernel"] in (1, 2, 5, 6)]   # tiles and diagonal runs
+    assert direct and any(sched[i]["kernel"] == 6 for i in runs) and any(sched[i]["kernel"] == 1 for i in runs)
     sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     ref = sv.tensor.clone()
@@ -230,7 +230,7 @@ def test_pass_shapes_and_tuner(dtype):
     for j, i in enumerate(direct):
         fc.set_pass_shape(dtype, i, *shapes[j % len(shapes)])
     assert fc.pass_shape(dtype, direct[0]) == shapes[0]
-    run_rots = [1, 3, 6, 7, 12]
+    run_rots = [1, 3, 6, 7, 12, 4, 2]
     for j, i in enumerate(runs):
         fc.set_pass_shape(dtype, i, run_rots[j % len(run_rots)], -1)
     sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
@@ -247,7 +247,7 @@ def test_pass_shapes_and_tuner(dtype):
     sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     torch.cuda.synchronize()
-    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, diagonal runs {runs}, tuned {chosen_runs}, "
+    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, tiles and diagonal runs {runs}, tuned {chosen_runs}, "
          f"ms {before:.4f} -> {after:.4f}")
     assert 0 < after <= before
     assert torch.equal(sv.tensor, ref)
