@@ -5,8 +5,8 @@ Workload: 30-qubit QFT (30 H + 435 controlled-phase + 15 SWAP gates) applied
 to a random normalised state with i.i.d. complex Gaussian amplitudes, after
 host fusion with k_max = 5.  One step = one application of the whole fused
 circuit (every fused gate = one in-place pass over the 2^30 amplitudes), with
-the state already resident in HBM.  Before the warmup the direct passes'
-launch shapes are measured on the state (circuit_tune, extras.<dtype>.tune),
+the state already resident in HBM.  Before the warmup the passes' launch
+shapes are measured on the state (circuit_tune, extras.<dtype>.tune),
 which is then drawn again from its seed; marker dispatches bracket the timed
 steps so that kernel traces can be cut to them (--summarize-kernel-trace on a
 per-dispatch trace).
@@ -465,7 +465,7 @@ def run_dense(n=32, depth=20, steps=1, warmup=1, tune_reps=2):
     """Dense random circuit (20 layers of Haar gates on 6- and 5-qubit random
     subsets, complex128, from |0...0>): per-pass kernel throughput; dense
     6-qubit passes are FP64-compute-bound, 5-qubit passes HBM-bound.  With
-    tune_reps > 0 the 5-qubit passes' unit order is first chosen per pass by
+    tune_reps > 0 every pass's unit order is first chosen per pass by
     measurement (circuit_tune), then the state is reset."""
     import numpy as np
     import torch
@@ -902,7 +902,7 @@ def main():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--k-max", type=int, default=5)
     ap.add_argument("--tune-reps", type=int, default=3,
-                    help="launches per candidate shape when tuning the QFT's direct passes (0: knob shapes)")
+                    help="launches per candidate shape when tuning the QFT's passes (0: knob shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-vqa", action="store_true")
