@@ -197,17 +197,17 @@ cast_status circuit_passes(const cast_fused *f, int n, cast_dtype dt, size_t *n_
 cast_status circuit_pass_info(const cast_fused *f, int n, cast_dtype dt, size_t i, size_t *first, size_t *count,
                               int *kernel, int *tables, double *alg_bytes, double *flops);
 
-/* Launch shapes of the passes of kernels 0, 1, 2, 4, 5 and 6 (every kind but
- * the elementwise diagonal).  A direct pass (0) walks its (group, block)
- * work items in runs of 2^chunk_log groups of one block and visits its
- * 2^it_bits iterations in an order rotated left by rot bits (rot 0: address
- * order; needs a power-of-two iteration count, else 0).  The others take
- * only rot (chunk_log is ignored): an LDS-tile pass (1, 2, 5) rotates the
- * order of its tiles, a matrix-core direct pass (4) that of its runs of four
- * 16-group units, and a diagonal run (6; on more than 8 qubits for
- * complex128, 9 for complex64, with diag_run_reuse > 0) that of its units of
- * one 4 KiB span repeated over 2^diag_run_reuse free high bits; a rotation
- * at or above the order's bit count is ignored.  Which rate a shape reaches depends on how the gate's planes
+/* Launch shapes of the passes (kernels 0 to 6).  A direct pass (0) walks
+ * its (group, block) work items in runs of 2^chunk_log groups of one block
+ * and visits its 2^it_bits iterations in an order rotated left by rot bits
+ * (rot 0: address order; needs a power-of-two iteration count, else 0).  The
+ * others take only rot (chunk_log is ignored): an LDS-tile pass (1, 2, 5)
+ * rotates the order of its tiles, an elementwise diagonal pass (3) that of
+ * the tiles of each active pattern, a matrix-core direct pass (4) that of its
+ * runs of four 16-group units, and a diagonal run (6; on more than 8 qubits
+ * for complex128, 9 for complex64, with diag_run_reuse > 0) that of its
+ * units of one 4 KiB span repeated over 2^diag_run_reuse free high bits; a
+ * rotation at or above the order's bit count is ignored.  Which rate a shape reaches depends on how the gate's planes
  * fall onto the DRAM channels and banks, so no one knob value suits every
  * pass (the paper's cost model is likewise measured, Sec. III-C).  The shape is kept
  * per pass in the list's schedule for (n, dt); -1 means the knob's value

@@ -809,13 +809,11 @@ cast_status circuit_tune(cast_sv *sv, cast_fused *fc, int reps, double *before_m
         SchedPass &sp = sc->passes[i];
         // diagonal runs in the unit-reuse kernel: unit-order rotation only
         const bool drun = sp.kind == 6 && tu.diag_run_reuse[dt] > 0 && n > (dt == CAST_C128 ? 8 : 9);
-        if ((sp.kind < 0 || sp.kind > 5 || sp.kind == 3) && !drun) continue;
+        if ((sp.kind < 0 || sp.kind > 5) && !drun) continue;
         const PassPlan &pl = f->plans[sp.first];
         const int kind = drun ? 6 : pass_kernel_kind(n, dt, pl);
-        // matrix-core direct passes, LDS-tile passes and diagonal runs take a
-        // unit- or tile-order rotation only
-        const bool rot_only = kind == 1 || kind == 2 || kind == 4 || kind == 5 || drun;
-        if (kind != 0 && !rot_only) continue;
+        // every kind but the direct one takes a unit- or tile-order rotation only
+        const bool rot_only = kind != 0;
         const int k = pl.k;
         // the knobs' shape first, then run lengths (direct passes), then
         // rotations at the best run length (8 for rotation-only passes)

@@ -247,6 +247,7 @@ __global__ void __launch_bounds__(256) k_diag(R *__restrict__ psi_r, const R *__
             rest = t / a.npat;
             pat = t - rest * a.npat;
         }
+        if (a.rot) rest = ((rest << a.rot) | (rest >> (a.rest_bits - a.rot))) & ((1u << a.rest_bits) - 1);
         const uint64_t tile = deposit(rest, a.hlowmask, a.kh) | a.patoff[pat];
         native_u4 w[U];
         uint32_t ju[U];
@@ -1145,6 +1146,7 @@ cast_status launch_pass(void *psi, int n, cast_dtype dt, const PassPlan &p, cons
             }
             g.npat = (uint32_t)npat;
             g.ntiles = (uint64_t)npat << g.rest_bits;
+            if (shape && shape->rot > 0 && shape->rot < g.rest_bits) g.rot = shape->rot;
             grid = g.ntiles;
             if (grid == 0) return CAST_OK;   // every phase is 1
         }

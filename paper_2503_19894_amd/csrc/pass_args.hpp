@@ -43,6 +43,7 @@ struct DiagArgs {
     int rest_bits;
     int pattern_major;
     int spread;             // tile number -> XCD by the XOR of its 3-bit digits (else round-robin)
+    int rot;                // the other tile bits rotated left by rot of rest_bits (0: in order)
     uint32_t npat;          // active patterns
     uint32_t patoff[64];    // tile-index bits of each active pattern
 };

@@ -204,10 +204,10 @@ def test_direct_rotated_order(dtype, rot):
 @pytest.mark.parametrize("dtype", DTYPES, ids=["c128", "c64"])
 def test_pass_shapes_and_tuner(dtype):
     """Per-pass launch shapes set by hand on every direct pass (rotation,
-    block-run length) and every LDS-tile pass and diagonal run (rotation,
-    including rotations the host must ignore), and the shapes the tuner picks:
-    the same circuit gives bitwise the same state as with the knobs' shapes,
-    and matches the oracle."""
+    block-run length) and every LDS-tile, diagonal and diagonal-run pass
+    (rotation, including rotations the host must ignore), and the shapes the
+    tuner picks: the same circuit gives bitwise the same state as with the
+    knobs' shapes, and matches the oracle."""
     n = 17
     rng = np.random.default_rng(29)
     gates = qft(n)
@@ -221,8 +221,8 @@ def test_pass_shapes_and_tuner(dtype):
     fc = cast.FusedCircuit(n, gates, k_max=4)
     sched = fc.schedule(dtype)
     direct = [i for i, p in enumerate(sched) if p["kernel"] == 0]
-    runs = [i for i, p in enumerate(sched) if p["kernel"] in (1, 2, 5, 6)]   # tiles and diagonal runs
-    assert direct and any(sched[i]["kernel"] == 6 for i in runs) and any(sched[i]["kernel"] == 1 for i in runs)
+    runs = [i for i, p in enumerate(sched) if p["kernel"] in (1, 2, 3, 5, 6)]   # tiles and diagonals
+    assert direct and all(any(sched[i]["kernel"] == kk for i in runs) for kk in (1, 3, 6))
     sv = cast.StateVector(n, tensor=torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     ref = sv.tensor.clone()
@@ -247,7 +247,7 @@ def test_pass_shapes_and_tuner(dtype):
     sv.tensor.copy_(torch.tensor(psi0, dtype=dtype, device="cuda"))
     sv.apply_circuit(fc)
     torch.cuda.synchronize()
-    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, tiles and diagonal runs {runs}, tuned {chosen_runs}, "
+    note(f"pass shapes {dtype}: direct passes {direct}, tuned {chosen}, tiles and diagonals {runs}, tuned {chosen_runs}, "
          f"ms {before:.4f} -> {after:.4f}")
     assert 0 < after <= before
     assert torch.equal(sv.tensor, ref)
